@@ -1,0 +1,214 @@
+/*
+ * mttkrp.h - C ABI of the MI355X (gfx950) all-mode sparse MTTKRP library.
+ *
+ * The library computes, for an N-mode sparse tensor X in coordinate (COO)
+ * form and dense factor matrices A_0..A_{N-1} (each I_w x R, row-major),
+ *
+ *   M_n(i, r) = sum over nonzeros e with c_n(e) = i of
+ *               val(e) * prod_{w != n} A_w(c_w(e), r)
+ *
+ * along every mode n (the elementwise spMTTKRP update of Sec. II-C and
+ * Eq. 4 of Wijeratne, Kannan, Prasanna, "Dynasor", arXiv 2309.09131), with
+ * the paper's dynamic tensor remapping (Sec. III-B): the nonzeros are kept
+ * in one buffer ordered for the mode being computed and, while mode n is
+ * computed, copied into the order of mode (n+1) mod N (Alg. "Dynasor",
+ * dynamic remapping store), so that two tensor-sized buffers serve all
+ * modes.  Around it: one CP-ALS sweep (Alg. "cp-als"), and the sampled CP
+ * loss sum_e (x_e - sum_r prod_n A_n(c_n(e), r))^2 with its gradient.
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are HIP device pointers (device memory of the GPU
+ *     that is current when the call is made); all others are host pointers.
+ *   - The caller owns every device allocation (workspace, tensor, factors,
+ *     outputs).  The library never allocates device memory; a plan owns
+ *     only a small host object and HIP events.
+ *   - `stream` is a hipStream_t passed as void* (NULL = legacy default
+ *     stream).  Except mttkrp_plan (synchronous), calls only enqueue work
+ *     on `stream` and return; a plan must be used by one stream at a time.
+ *   - Factor matrices are row-major I_w x R, FP32 (MTTKRP_F32) or BF16
+ *     (MTTKRP_BF16, stored bfloat16, widened to FP32 in registers).  MTTKRP
+ *     outputs and gradients are FP32, row-major I_n x R.
+ *   - Errors are status codes; nothing aborts or throws across the ABI.
+ *     Argument errors are detected on the host before any device work.
+ *   - Limits: 2 <= N <= 8, 1 <= R <= 256, 1 <= I_n < 2^31, nnz < 2^31.
+ *   - Results are deterministic: no global atomics, fixed reduction order,
+ *     so repeated calls give bit-identical outputs.
+ */
+#ifndef MTTKRP_H
+#define MTTKRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTTKRP_MAX_MODES 8
+#define MTTKRP_MAX_RANK 256
+
+typedef struct mttkrp_plan_s *mttkrp_plan_t;
+
+typedef enum {
+    MTTKRP_OK = 0,
+    MTTKRP_EINVAL = 1,  /* bad argument (null pointer, size, mode, dtype) */
+    MTTKRP_ERANGE = 2,  /* a coordinate is outside [0, I_n)               */
+    MTTKRP_ENOMEM = 3,  /* workspace smaller than mttkrp_plan_workspace  */
+    MTTKRP_ESTATE = 4,  /* tensor is in another mode's layout and the plan
+                           was built with MTTKRP_NO_IMPLICIT_REMAP        */
+    MTTKRP_EHIP = 5     /* a HIP call failed; see mttkrp_last_error      */
+} mttkrp_status;
+
+typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
+
+/* flags */
+#define MTTKRP_NO_IMPLICIT_REMAP 1u  /* mttkrp_mode on another layout fails  */
+#define MTTKRP_NATURAL_ORDER 2u      /* dispatch shards in tensor order
+                                        instead of longest-first order     */
+
+/* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
+typedef struct {
+    int32_t g;                       /* nonzeros per shard; default 1024     */
+    int32_t m[MTTKRP_MAX_MODES];     /* indices per super-shard, per mode:
+                                        default follows Sec. V-A: 1 when
+                                        I_n < workers, else I_n / (q*workers)
+                                        kept in (1000, 16000) when possible  */
+    int32_t workers;                 /* nu: scheduling bins; default 256     */
+    uint32_t flags;
+} mttkrp_plan_opts;
+
+/* Bytes of device workspace a plan needs (ws_bytes for mttkrp_plan).
+ * Layout-independent upper bound; depends on N, dims, nnz, rank, opts. */
+mttkrp_status mttkrp_plan_workspace(int nmodes, const int64_t *dims, int64_t nnz,
+                                    int rank, const mttkrp_plan_opts *opts,
+                                    size_t *bytes);
+
+/*
+ * Preprocess a COO tensor (Sec. III-A partitions, Sec. V-J preprocessing).
+ *   d_idx   [nmodes][nnz] int32, mode-major, 0-based coordinates.
+ *   d_vals  [nnz] float values.  Duplicated coordinates are accepted and
+ *           summed by every MTTKRP.
+ * Builds, inside d_workspace: the mode-0 layout L_0 (nonzeros ordered by
+ * (c_0, c_{N-1}, ..., c_1, input position)), for every mode n the remap
+ * target P_n (slot of each L_n element in L_{n+1}), row pointers, the
+ * super-shard / shard tables and the longest-first schedule (Alg.
+ * "ss_scheduling").  The inputs are copied; they may be freed afterwards.
+ * The workspace must stay allocated and untouched while the plan lives.
+ * Synchronous: returns after the device work finished.  ERANGE if a
+ * coordinate is out of range (nothing else is then valid).
+ */
+mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz,
+                          const int32_t *d_idx, const float *d_vals, int rank,
+                          const mttkrp_plan_opts *opts, void *d_workspace,
+                          size_t ws_bytes, void *stream, mttkrp_plan_t *out);
+
+/*
+ * MTTKRP along one mode (Eq. 4).  d_factors: host array of nmodes device
+ * pointers (the output mode's factor is read only by cp_loss_grad and may
+ * be NULL here).  d_out: I_mode x R FP32, fully overwritten (rows without
+ * nonzeros become +0.0).  If the tensor is not in L_mode it is first
+ * remapped forward (ESTATE instead under MTTKRP_NO_IMPLICIT_REMAP).
+ * fuse_remap != 0 also writes L_{mode+1} in the same pass (Sec. III-B;
+ * Sec. V-B: remap done by the computing agent) and leaves the plan there.
+ */
+mttkrp_status mttkrp_mode(mttkrp_plan_t p, int mode, const void *const *d_factors,
+                          mttkrp_dtype fdt, float *d_out, int fuse_remap,
+                          void *stream);
+
+/* MTTKRP along all modes n = 0..N-1 with fused remapping (Alg. "Dynasor");
+ * every mode uses the given factors.  d_out: host array of nmodes device
+ * pointers, each I_n x R FP32.  Starts from L_0 (remapping first if needed)
+ * and ends in L_0. */
+mttkrp_status mttkrp_all_modes(mttkrp_plan_t p, const void *const *d_factors,
+                               mttkrp_dtype fdt, float *const *d_out,
+                               void *stream);
+
+/* Standalone remapping (Sec. III-B): advance the layout L_cur -> L_cur+1 ->
+ * ... -> L_to_mode.  No-op when already there. */
+mttkrp_status remap(mttkrp_plan_t p, int to_mode, void *stream);
+
+/*
+ * Sampled CP loss L = sum_e (x_e - m_e)^2, m_e = sum_r prod_n A_n(c_n(e), r)
+ * (the CP model of Eq. 1 evaluated at the stored nonzeros; no 1/2, no
+ * mean), and optionally its gradient
+ *   dL/dA_k(i, r) = -2 * s * sum_{e: c_k(e) = i} rho_e prod_{n != k} A_n(c_n(e), r)
+ * with rho_e = x_e - m_e recomputed per pass (never stored) and s the
+ * scale *d_grad_scale (NULL: 1.0; a device double, e.g. the upstream
+ * gradient of an autograd graph).
+ *   d_loss   device double or NULL.
+ *   d_grads  host array of nmodes device pointers (I_k x R FP32) or NULL.
+ * With gradients: N residual-MTTKRP passes with fused remap, ending in the
+ * layout it started in.  Loss only: one pass, layout unchanged.
+ */
+mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors,
+                           mttkrp_dtype fdt, double *d_loss, float *const *d_grads,
+                           const double *d_grad_scale, void *stream);
+
+/*
+ * One CP-ALS sweep (Alg. "cp-als"), Gauss-Seidel over n = 0..N-1:
+ *   M_n = MTTKRP(n) with fused remap; V = hadamard_{w != n} A_w^T A_w;
+ *   A_n = M_n V^{-1} (Cholesky, FP64); lambda_r = ||A_n(:, r)||_2,
+ *   A_n(:, r) /= lambda_r (zero columns left as is); store A_n in fdt
+ *   (BF16: round to nearest even); G_n = A_n^T A_n of the stored values.
+ * Gram matrices, Cholesky, solve and the norm / fit reductions run in FP64.
+ *   d_factors  in/out, host array of nmodes device pointers (fdt).
+ *   d_mbuf     FP32 scratch of max_n I_n x R elements.
+ *   d_lambda   device double[R], lambda of the last mode.
+ *   d_fit      device double or NULL: 1 - ||X - Xhat||_F / ||X||_F.
+ * If a Cholesky factorisation fails, 1e-12 * trace(V) / R is added to the
+ * diagonal once (counted in the MTTKRP_INFO_RIDGE info after a sync).
+ */
+mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors,
+                           mttkrp_dtype fdt, float *d_mbuf, double *d_lambda,
+                           double *d_fit, void *stream);
+
+/* Device-side plan arrays, copied into caller memory (for parity tests). */
+enum {
+    MTTKRP_Q_LAYOUT = 0,   /* current element buffer: nnz x (N int32 + f32) */
+    MTTKRP_Q_PERM = 1,     /* P_mode: nnz int32                              */
+    MTTKRP_Q_ROW_PTR = 2,  /* I_mode + 1 int32                               */
+    MTTKRP_Q_SHARDS = 3,   /* nshards x {start, len, super-shard} int32      */
+    MTTKRP_Q_LPT = 4       /* k_mode int32: scheduling bin of each super-shard */
+};
+/* Copies the array `what` of `mode` into dst (device or host memory,
+ * hipMemcpyDefault; synchronises `stream`).  Sizes in bytes: LAYOUT
+ * nnz*(N+1)*4 (the layout the tensor is currently in), PERM nnz*4, ROW_PTR
+ * (I_mode+1)*4, SHARDS nshards*12, LPT k_mode*4.  EINVAL if bytes is
+ * smaller. */
+mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst,
+                                size_t bytes, void *stream);
+
+/* Host-side scalars. */
+enum {
+    MTTKRP_INFO_CUR_MODE = 0,     /* layout the tensor is in                 */
+    MTTKRP_INFO_NSHARDS = 1,      /* shards of `mode`                        */
+    MTTKRP_INFO_NSUPER = 2,       /* super-shards of `mode` (k_n)            */
+    /* 3: reserved */
+    MTTKRP_INFO_NSPLIT = 4,       /* rows of `mode` split across shards      */
+    MTTKRP_INFO_G = 5,            /* shard size used                         */
+    MTTKRP_INFO_M = 6,            /* super-shard size of `mode`              */
+    MTTKRP_INFO_RIDGE = 7         /* ridge count of the last cp_als_sweep
+                                     (reads device memory; synchronises)    */
+};
+mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *value);
+
+/* Kernel timing with HIP events on the launch stream: when enabled, every
+ * per-mode MTTKRP kernel launch is bracketed by events.  mttkrp_profile_read
+ * synchronises, returns the summed milliseconds and launch count of that
+ * kernel for `mode` (-1: all modes) since the last reset, and resets. */
+mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable);
+mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms,
+                                  int64_t *launches);
+
+/* Frees the host object (never the caller's workspace). */
+mttkrp_status mttkrp_plan_destroy(mttkrp_plan_t p);
+
+const char *mttkrp_status_str(mttkrp_status st);
+/* Text of the last error on `p` (or of the last plan-less error when p is
+ * NULL); valid until the next call on the same plan. */
+const char *mttkrp_last_error(mttkrp_plan_t p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTTKRP_H */

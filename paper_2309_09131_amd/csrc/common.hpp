@@ -1,0 +1,60 @@
+// Shared device helpers for the gfx950 kernels: packed nonzero records,
+// BF16 <-> FP32 conversion, wave64 shuffles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WAVE 64
+
+// One nonzero: N int32 coordinates followed by the FP32 value (4N+4 bytes).
+// Packed with 4-byte alignment; gfx950 global loads/stores of 16 bytes only
+// need dword alignment, so the compiler emits dwordx4 (+dword/dwordx2).
+template <int N>
+struct __attribute__((packed, aligned(4))) Rec {
+    uint32_t w[N + 1];
+};
+
+template <int N>
+__device__ __forceinline__ Rec<N> load_rec(const uint32_t *__restrict__ buf, int64_t i)
+{
+    return *reinterpret_cast<const Rec<N> *>(buf + i * (N + 1));
+}
+
+template <int N>
+__device__ __forceinline__ void store_rec(uint32_t *__restrict__ buf, int64_t i, const Rec<N> &r)
+{
+    *reinterpret_cast<Rec<N> *>(buf + i * (N + 1)) = r;
+}
+
+// bfloat16 storage <-> float.  Widening is exact (the 16 high bits).
+__device__ __forceinline__ float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (uint16_t)((u >> 16) | 0x0040u);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __shfl_xor(lo, m);
+    hi = __shfl_xor(hi, m);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+    return v;
+}
+
+static inline int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }

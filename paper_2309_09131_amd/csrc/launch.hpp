@@ -1,0 +1,66 @@
+// Kernel argument block and the per-mode-count launchers.  Each launcher is
+// defined (explicitly specialised) in inst_n<N>.hip, one translation unit
+// per number of modes, so the template kernels compile in parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mk {
+
+struct Args {
+    const uint32_t *rin;      // L_n records
+    uint32_t *rout;           // L_{n+1} records, or nullptr (no remap)
+    const int32_t *perm;      // P_n
+    const int32_t *row_ptr;   // I_n + 1
+    const int32_t *shards;    // [nshards][3] = start, len, super-shard
+    const int32_t *order;     // dispatch order of shards, or nullptr
+    int32_t nshards;
+    int32_t mode;
+    int32_t R;
+    int32_t pad_;
+    const void *fac[8];       // factor matrices (I_w x R row-major)
+    float *out;               // I_n x R
+    float *carry;             // [nshards][2][R] boundary partials
+    const double *gscale;     // residual variant: upstream scale or nullptr
+    double *partial;          // loss forward: one double per shard
+};
+
+// Lane configuration: contiguous (lanes = nextpow2(R / V), V = 16 bytes of
+// factor row per lane) or strided (64 lanes, J = ceil(R / 64) ranks each).
+struct LaneCfg {
+    int lanes;
+    int j;
+    bool strided;
+};
+
+enum Kind { KIND_MTTKRP = 0, KIND_RESID = 1, KIND_LOSS = 2 };
+
+template <int N>
+hipError_t launch_mttkrp(const Args &a, int bf16, LaneCfg c, int kind, unsigned grid,
+                         hipStream_t s);
+template <int N>
+hipError_t launch_remap(const uint32_t *rin, uint32_t *rout, const int32_t *perm, int64_t nnz,
+                        hipStream_t s);
+template <int N>
+hipError_t launch_pack(const int32_t *idx, const float *vals, const int32_t *o, int64_t nnz,
+                       uint32_t *rec, hipStream_t s);
+
+#define MK_DECLARE(N)                                                                      \
+    template <>                                                                            \
+    hipError_t launch_mttkrp<N>(const Args &, int, LaneCfg, int, unsigned, hipStream_t);   \
+    template <>                                                                            \
+    hipError_t launch_remap<N>(const uint32_t *, uint32_t *, const int32_t *, int64_t,     \
+                               hipStream_t);                                               \
+    template <>                                                                            \
+    hipError_t launch_pack<N>(const int32_t *, const float *, const int32_t *, int64_t,    \
+                              uint32_t *, hipStream_t);
+MK_DECLARE(2)
+MK_DECLARE(3)
+MK_DECLARE(4)
+MK_DECLARE(5)
+MK_DECLARE(6)
+MK_DECLARE(7)
+MK_DECLARE(8)
+#undef MK_DECLARE
+
+}  // namespace mk

@@ -1,0 +1,943 @@
+// Host side of the C ABI declared in include/mttkrp.h: argument checks,
+// workspace carve-up, plan construction (device sorts + host partition
+// tables), and the launch sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "als_kernels.hpp"
+#include "common.hpp"
+#include "launch.hpp"
+#include "mttkrp.h"
+#include "plan_kernels.hpp"
+
+namespace {
+
+constexpr int DEFAULT_G = 1024;
+constexpr int DEFAULT_WORKERS = 256;
+constexpr int GRAM_TARGET_BLOCKS = 1024;
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    int N;
+    int64_t dims[MTTKRP_MAX_MODES];
+    int64_t nnz;
+    int R;
+    int g;
+    int workers;
+    uint32_t flags;
+    int64_t m[MTTKRP_MAX_MODES], k[MTTKRP_MAX_MODES], maxS[MTTKRP_MAX_MODES];
+    size_t off_rec[2], off_perm[MTTKRP_MAX_MODES], off_rp[MTTKRP_MAX_MODES];
+    size_t off_sh[MTTKRP_MAX_MODES], off_ord[MTTKRP_MAX_MODES], off_split[MTTKRP_MAX_MODES];
+    size_t off_lpt[MTTKRP_MAX_MODES];
+    size_t off_xx, off_misc;           // persistent scalars
+    size_t off_scratch, scratch_bytes, total;
+    // runtime scratch (inside scratch)
+    size_t rt_carry, rt_partial, rt_G, rt_L, rt_Linv, rt_W, rt_gpart, rt_colsq, rt_lambda_tmp;
+    // plan scratch (inside scratch)
+    size_t ps_k0, ps_k1, ps_v0, ps_v1, ps_o0, ps_o1, ps_hist, ps_hscan, ps_sums, ps_err;
+};
+
+int64_t default_m(int64_t I, int workers)
+{
+    if (I < workers) return 1;
+    int64_t q = 1;
+    int64_t m = (I + workers - 1) / workers;
+    if (m > 16000) {
+        q = (I + (int64_t)workers * 16000 - 1) / ((int64_t)workers * 16000);
+        m = (I + q * workers - 1) / (q * workers);
+    }
+    return m;
+}
+
+mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
+                             const mttkrp_plan_opts *opts, Layout *L, std::string *why)
+{
+    if (N < 2 || N > MTTKRP_MAX_MODES) { *why = "nmodes must be in [2, 8]"; return MTTKRP_EINVAL; }
+    if (!dims) { *why = "dims is NULL"; return MTTKRP_EINVAL; }
+    if (R < 1 || R > MTTKRP_MAX_RANK) { *why = "rank must be in [1, 256]"; return MTTKRP_EINVAL; }
+    if (nnz < 0 || nnz >= (int64_t(1) << 31)) { *why = "nnz must be in [0, 2^31)"; return MTTKRP_EINVAL; }
+    memset(L, 0, sizeof(*L));
+    L->N = N; L->nnz = nnz; L->R = R;
+    L->g = (opts && opts->g > 0) ? opts->g : DEFAULT_G;
+    L->workers = (opts && opts->workers > 0) ? opts->workers : DEFAULT_WORKERS;
+    L->flags = opts ? opts->flags : 0u;
+    if (opts && opts->g < 0) { *why = "g must be >= 0"; return MTTKRP_EINVAL; }
+    for (int n = 0; n < N; ++n) {
+        if (dims[n] < 1 || dims[n] >= (int64_t(1) << 31)) {
+            *why = "every dimension must be in [1, 2^31)";
+            return MTTKRP_EINVAL;
+        }
+        L->dims[n] = dims[n];
+        if (opts && opts->m[n] < 0) { *why = "m[n] must be >= 0"; return MTTKRP_EINVAL; }
+        L->m[n] = (opts && opts->m[n] > 0) ? opts->m[n] : default_m(dims[n], L->workers);
+        if (L->m[n] > dims[n]) L->m[n] = dims[n];
+        L->k[n] = (dims[n] + L->m[n] - 1) / L->m[n];
+        L->maxS[n] = (nnz + L->g - 1) / L->g + L->k[n];
+    }
+    const int NW = N + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L->off_rec[0] = take((size_t)nnz * NW * 4);
+    L->off_rec[1] = take((size_t)nnz * NW * 4);
+    for (int n = 0; n < N; ++n) L->off_perm[n] = take((size_t)nnz * 4);
+    for (int n = 0; n < N; ++n) L->off_rp[n] = take((size_t)(dims[n] + 1) * 4);
+    int64_t maxS = 0;
+    for (int n = 0; n < N; ++n) {
+        L->off_sh[n] = take((size_t)L->maxS[n] * 12);
+        L->off_ord[n] = take((size_t)L->maxS[n] * 4);
+        L->off_split[n] = take((size_t)L->maxS[n] * 16);
+        L->off_lpt[n] = take((size_t)L->k[n] * 4);
+        maxS = std::max(maxS, L->maxS[n]);
+    }
+    L->off_xx = take(64);
+    L->off_misc = take(64);                    // ridge counter, fail flag
+    L->off_scratch = off;
+    // runtime scratch
+    size_t r0 = 0;
+    auto rtake = [&](size_t bytes) { size_t o = r0; r0 = align_up(r0 + bytes); return o; };
+    L->rt_carry = rtake((size_t)maxS * 2 * R * 4);
+    L->rt_partial = rtake((size_t)std::max<int64_t>(maxS, 4096) * 8);
+    L->rt_G = rtake((size_t)N * R * R * 8);
+    L->rt_L = rtake((size_t)R * R * 8);
+    L->rt_Linv = rtake((size_t)R * R * 8);
+    L->rt_W = rtake((size_t)R * R * 8);
+    L->rt_gpart = rtake((size_t)GRAM_TARGET_BLOCKS * 256 * 8 + (size_t)R * R * 8);
+    L->rt_colsq = rtake((size_t)als::APPLY_BLOCKS * R * 8);
+    L->rt_lambda_tmp = rtake((size_t)R * 8 + 64);
+    // plan scratch
+    size_t p0 = 0;
+    auto ptake = [&](size_t bytes) { size_t o = p0; p0 = align_up(p0 + bytes); return o; };
+    const int64_t ntiles = (nnz + plan::TILE - 1) / plan::TILE;
+    const int64_t hlen = 256 * std::max<int64_t>(ntiles, 1);
+    L->ps_k0 = ptake((size_t)nnz * 4);
+    L->ps_k1 = ptake((size_t)nnz * 4);
+    L->ps_v0 = ptake((size_t)nnz * 4);
+    L->ps_v1 = ptake((size_t)nnz * 4);
+    L->ps_o0 = ptake((size_t)nnz * 4);
+    L->ps_o1 = ptake((size_t)nnz * 4);
+    L->ps_hist = ptake((size_t)hlen * 4);
+    L->ps_hscan = ptake((size_t)hlen * 4);
+    L->ps_sums = ptake((size_t)((hlen + plan::SCAN_CHUNK - 1) / plan::SCAN_CHUNK + 1) * 4);
+    L->ps_err = ptake(64);
+    L->scratch_bytes = std::max(r0, p0);
+    L->total = L->off_scratch + L->scratch_bytes;
+    return MTTKRP_OK;
+}
+
+struct ProfEvent { hipEvent_t a, b; int mode; };
+
+}  // namespace
+
+struct mttkrp_plan_s {
+    Layout L;
+    char *ws = nullptr;
+    int cur = 0;            // layout the tensor is in
+    int buf = 0;            // record buffer holding it
+    int64_t nshards[MTTKRP_MAX_MODES] = {};
+    int64_t nsplit[MTTKRP_MAX_MODES] = {};
+    int64_t nempty[MTTKRP_MAX_MODES] = {};
+    std::string err;
+    bool prof = false;
+    std::vector<ProfEvent> events;
+    std::vector<hipEvent_t> pool;
+
+    uint32_t *rec(int b) { return reinterpret_cast<uint32_t *>(ws + L.off_rec[b]); }
+    int32_t *perm(int n) { return reinterpret_cast<int32_t *>(ws + L.off_perm[n]); }
+    int32_t *rp(int n) { return reinterpret_cast<int32_t *>(ws + L.off_rp[n]); }
+    int32_t *sh(int n) { return reinterpret_cast<int32_t *>(ws + L.off_sh[n]); }
+    int32_t *ord(int n) { return reinterpret_cast<int32_t *>(ws + L.off_ord[n]); }
+    int32_t *split(int n) { return reinterpret_cast<int32_t *>(ws + L.off_split[n]); }
+    int32_t *lpt(int n) { return reinterpret_cast<int32_t *>(ws + L.off_lpt[n]); }
+    double *xx() { return reinterpret_cast<double *>(ws + L.off_xx); }
+    int32_t *ridge() { return reinterpret_cast<int32_t *>(ws + L.off_misc); }
+    int32_t *fail() { return reinterpret_cast<int32_t *>(ws + L.off_misc) + 1; }
+    template <typename T> T *rt(size_t o) { return reinterpret_cast<T *>(ws + L.off_scratch + o); }
+};
+
+static std::string g_last_error;
+
+#define HIPCHK(p, call)                                                        \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) {                                                \
+            set_err((p), std::string(#call) + ": " + hipGetErrorString(e_));   \
+            return MTTKRP_EHIP;                                                \
+        }                                                                      \
+    } while (0)
+
+static void set_err(mttkrp_plan_t p, const std::string &s)
+{
+    if (p) p->err = s;
+    else g_last_error = s;
+}
+
+static mttkrp_status fail(mttkrp_plan_t p, mttkrp_status st, const std::string &s)
+{
+    set_err(p, s);
+    return st;
+}
+
+static unsigned grid_for(int64_t n, int per = 256, unsigned cap = 65536)
+{
+    int64_t g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+// ---------------------------------------------------------------- kernels
+// launch dispatch by mode count
+
+static hipError_t launch_mttkrp_any(int N, const mk::Args &a, int bf16, mk::LaneCfg c, int kind,
+                                    unsigned grid, hipStream_t s)
+{
+    switch (N) {
+    case 2: return mk::launch_mttkrp<2>(a, bf16, c, kind, grid, s);
+    case 3: return mk::launch_mttkrp<3>(a, bf16, c, kind, grid, s);
+    case 4: return mk::launch_mttkrp<4>(a, bf16, c, kind, grid, s);
+    case 5: return mk::launch_mttkrp<5>(a, bf16, c, kind, grid, s);
+    case 6: return mk::launch_mttkrp<6>(a, bf16, c, kind, grid, s);
+    case 7: return mk::launch_mttkrp<7>(a, bf16, c, kind, grid, s);
+    case 8: return mk::launch_mttkrp<8>(a, bf16, c, kind, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_remap_any(int N, const uint32_t *rin, uint32_t *rout,
+                                   const int32_t *perm, int64_t nnz, hipStream_t s)
+{
+    switch (N) {
+    case 2: return mk::launch_remap<2>(rin, rout, perm, nnz, s);
+    case 3: return mk::launch_remap<3>(rin, rout, perm, nnz, s);
+    case 4: return mk::launch_remap<4>(rin, rout, perm, nnz, s);
+    case 5: return mk::launch_remap<5>(rin, rout, perm, nnz, s);
+    case 6: return mk::launch_remap<6>(rin, rout, perm, nnz, s);
+    case 7: return mk::launch_remap<7>(rin, rout, perm, nnz, s);
+    case 8: return mk::launch_remap<8>(rin, rout, perm, nnz, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t launch_pack_any(int N, const int32_t *idx, const float *vals, const int32_t *o,
+                                  int64_t nnz, uint32_t *rec, hipStream_t s)
+{
+    switch (N) {
+    case 2: return mk::launch_pack<2>(idx, vals, o, nnz, rec, s);
+    case 3: return mk::launch_pack<3>(idx, vals, o, nnz, rec, s);
+    case 4: return mk::launch_pack<4>(idx, vals, o, nnz, rec, s);
+    case 5: return mk::launch_pack<5>(idx, vals, o, nnz, rec, s);
+    case 6: return mk::launch_pack<6>(idx, vals, o, nnz, rec, s);
+    case 7: return mk::launch_pack<7>(idx, vals, o, nnz, rec, s);
+    case 8: return mk::launch_pack<8>(idx, vals, o, nnz, rec, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Zero fill and carry fix-up (mode-count independent).
+__global__ void fill_zero_kernel(float *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+// One block per row split across shards: adds the boundary partials of the
+// shards it spans in a fixed order (interleaved groups, then a tree) and
+// writes the row.  split[k] = {row, first shard, last shard, entry used in
+// the first shard}; later shards use entry 0.
+__global__ __launch_bounds__(256) void carry_fixup_kernel(const int32_t *__restrict__ split,
+                                                          const float *__restrict__ carry,
+                                                          float *__restrict__ out, int R, int RL)
+{
+    __shared__ float sh[256];
+    const int k = blockIdx.x;
+    const int row = split[4 * k], s0 = split[4 * k + 1], s1 = split[4 * k + 2],
+              e0 = split[4 * k + 3];
+    const int r = threadIdx.x % RL, q = threadIdx.x / RL, G = 256 / RL;
+    const int cnt = s1 - s0 + 1;
+    float acc = 0.0f;
+    if (r < R)
+        for (int i = q; i < cnt; i += G) {
+            const int64_t ent = (i == 0) ? (int64_t)s0 * 2 + e0 : (int64_t)(s0 + i) * 2;
+            acc += carry[ent * R + r];
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = G / 2; h >= 1; h >>= 1) {
+        if (q < h) sh[threadIdx.x] += sh[threadIdx.x + h * RL];
+        __syncthreads();
+    }
+    if (q == 0 && r < R) out[(int64_t)row * R + r] = sh[threadIdx.x];
+}
+
+// ---------------------------------------------------------------- helpers
+
+static int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+static mk::LaneCfg lane_cfg(int R, mttkrp_dtype fdt, const void *const *facs, int N,
+                            const float *out)
+{
+    const int V = (fdt == MTTKRP_BF16) ? 8 : 4;
+    bool ok = (R % V == 0) && (out == nullptr || aligned16(out));
+    for (int w = 0; w < N && ok; ++w)
+        if (facs[w] && !aligned16(facs[w])) ok = false;
+    if (ok && next_pow2(R / V) <= 64) return mk::LaneCfg{next_pow2(R / V), 1, false};
+    return mk::LaneCfg{64, (R + 63) / 64, true};
+}
+
+// Stable LSD radix sort of (keys, vals) pairs by the low `bits` of the key.
+// Input in (k0, v0); returns which buffer pair holds the result (0 or 1).
+static mttkrp_status radix_sort(mttkrp_plan_t p, int32_t *k0, int32_t *v0, int32_t *k1,
+                                int32_t *v1, int64_t n, int bits, hipStream_t s, int *which)
+{
+    const Layout &L = p->L;
+    const int64_t ntiles = (n + plan::TILE - 1) / plan::TILE;
+    const int64_t hlen = 256 * ntiles;
+    int32_t *hist = p->rt<int32_t>(L.ps_hist);
+    int32_t *hscan = p->rt<int32_t>(L.ps_hscan);
+    int32_t *sums = p->rt<int32_t>(L.ps_sums);
+    const int64_t nchunks = (hlen + plan::SCAN_CHUNK - 1) / plan::SCAN_CHUNK;
+    int cur = 0;
+    int32_t *K[2] = {k0, k1}, *Vv[2] = {v0, v1};
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(plan::radix_upsweep, dim3((unsigned)ntiles), dim3(256), 0, s, K[cur],
+                           n, shift, hist, (int)ntiles);
+        hipLaunchKernelGGL(plan::scan_reduce, dim3((unsigned)nchunks), dim3(256), 0, s, hist,
+                           hlen, sums);
+        hipLaunchKernelGGL(plan::scan_sums, dim3(1), dim3(256), 0, s, sums, nchunks);
+        hipLaunchKernelGGL(plan::scan_apply, dim3((unsigned)nchunks), dim3(256), 0, s, hist, hlen,
+                           sums, hscan);
+        hipLaunchKernelGGL(plan::radix_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, K[cur],
+                           Vv[cur], n, shift, hscan, (int)ntiles, K[cur ^ 1], Vv[cur ^ 1]);
+        HIPCHK(p, hipGetLastError());
+        cur ^= 1;
+    }
+    *which = cur;
+    return MTTKRP_OK;
+}
+
+static int key_bits(int64_t I)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < I) ++b;
+    return b;
+}
+
+// Host partition tables of one mode from its row pointers (Sec. III-A, IV-A).
+static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
+                         std::vector<int32_t> &shards, std::vector<int32_t> &order,
+                         std::vector<int32_t> &split, std::vector<int32_t> &lpt_bin,
+                         int64_t *nempty)
+{
+    const int64_t I = L.dims[n], m = L.m[n], k = L.k[n], g = L.g;
+    std::vector<int64_t> ss_first(k), ss_cnt(k);
+    shards.clear();
+    for (int64_t j = 0; j < k; ++j) {
+        const int64_t lo = j * m, hi = std::min(I, (j + 1) * m);
+        const int64_t a = rp[lo], b = rp[hi];
+        ss_first[j] = (int64_t)shards.size() / 3;
+        ss_cnt[j] = (b - a + g - 1) / g;
+        for (int64_t q = 0; q < ss_cnt[j]; ++q) {
+            shards.push_back((int32_t)(a + q * g));
+            shards.push_back((int32_t)std::min<int64_t>(g, b - a - q * g));
+            shards.push_back((int32_t)j);
+        }
+    }
+    const int64_t S = (int64_t)shards.size() / 3;
+    // longest-first scheduling of super-shards over `workers` bins
+    std::vector<int64_t> ord(k);
+    for (int64_t j = 0; j < k; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int64_t x, int64_t y) { return ss_cnt[x] > ss_cnt[y]; });
+    std::vector<int64_t> load(L.workers, 0);
+    lpt_bin.assign(k, 0);
+    for (int64_t a = 0; a < k; ++a) {
+        int best = 0;
+        for (int i = 1; i < L.workers; ++i)
+            if (load[i] < load[best]) best = i;
+        lpt_bin[ord[a]] = best;
+        load[best] += ss_cnt[ord[a]];
+    }
+    order.clear();
+    if (L.flags & MTTKRP_NATURAL_ORDER) {
+        for (int64_t s = 0; s < S; ++s) order.push_back((int32_t)s);
+    } else {
+        for (int64_t a = 0; a < k; ++a)
+            for (int64_t q = 0; q < ss_cnt[ord[a]]; ++q)
+                order.push_back((int32_t)(ss_first[ord[a]] + q));
+    }
+    // rows split across consecutive shards
+    auto row_of = [&](int64_t pos) {   // row r with rp[r] <= pos < rp[r+1]
+        auto it = std::upper_bound(rp.begin(), rp.end(), (int32_t)pos);
+        return (int64_t)(it - rp.begin()) - 1;
+    };
+    split.clear();
+    bool open = false;
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t st = shards[3 * s], en = st + shards[3 * s + 1];
+        const int64_t f = row_of(st), l = row_of(en - 1);
+        const bool sb = rp[f] < st, sa = rp[l + 1] > en;
+        if (sb) {                       // continues an open split row
+            split[split.size() - 2] = (int32_t)s;
+            if (!(l == f && sa)) open = false;
+        }
+        if (sa && !(l == f && sb)) {    // opens a new split row
+            split.push_back((int32_t)l);
+            split.push_back((int32_t)s);
+            split.push_back((int32_t)s);
+            split.push_back(l == f ? 0 : 1);
+            open = true;
+        }
+    }
+    (void)open;
+    int64_t ne = 0;
+    for (int64_t r = 0; r < I; ++r) ne += (rp[r] == rp[r + 1]);
+    *nempty = ne;
+}
+
+static mttkrp_status check_factors(mttkrp_plan_t p, const void *const *f, int skip_ok, int mode,
+                                   mttkrp_dtype fdt)
+{
+    if (!f) return fail(p, MTTKRP_EINVAL, "factor pointer array is NULL");
+    if (fdt != MTTKRP_F32 && fdt != MTTKRP_BF16) return fail(p, MTTKRP_EINVAL, "bad dtype");
+    for (int w = 0; w < p->L.N; ++w)
+        if (!f[w] && !(skip_ok && w == mode))
+            return fail(p, MTTKRP_EINVAL, "factor pointer is NULL for mode " + std::to_string(w));
+    return MTTKRP_OK;
+}
+
+static hipEvent_t take_event(mttkrp_plan_t p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Remap kernel run: L_cur -> L_cur+1.
+static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
+{
+    const Layout &L = p->L;
+    HIPCHK(p, launch_remap_any(L.N, p->rec(p->buf), p->rec(p->buf ^ 1), p->perm(p->cur), L.nnz, s));
+    p->buf ^= 1;
+    p->cur = (p->cur + 1) % L.N;
+    return MTTKRP_OK;
+}
+
+// One MTTKRP-family pass over the current layout (mode == p->cur).
+static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_dtype fdt,
+                              float *out, bool fuse, int kind, const double *gscale,
+                              hipStream_t s)
+{
+    const Layout &L = p->L;
+    const int n = p->cur;
+    const int64_t rows = L.dims[n];
+    if (kind != mk::KIND_LOSS && (p->nempty[n] > 0 || L.nnz == 0))
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(rows * L.R)), dim3(256), 0, s, out,
+                           rows * L.R);
+    if (L.nnz == 0) {
+        HIPCHK(p, hipGetLastError());
+        if (fuse) p->cur = (n + 1) % L.N;
+        return MTTKRP_OK;
+    }
+    mk::Args a;
+    memset(&a, 0, sizeof(a));
+    a.rin = p->rec(p->buf);
+    a.rout = fuse ? p->rec(p->buf ^ 1) : nullptr;
+    a.perm = p->perm(n);
+    a.row_ptr = p->rp(n);
+    a.shards = p->sh(n);
+    a.order = (kind == mk::KIND_LOSS) ? nullptr : p->ord(n);
+    a.nshards = (int32_t)p->nshards[n];
+    a.mode = n;
+    a.R = L.R;
+    for (int w = 0; w < L.N; ++w) a.fac[w] = facs[w];
+    a.out = out;
+    a.carry = p->rt<float>(L.rt_carry);
+    a.gscale = gscale;
+    a.partial = p->rt<double>(L.rt_partial);
+    const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
+    const unsigned grid = (unsigned)((p->nshards[n] + 3) / 4);
+    ProfEvent ev{nullptr, nullptr, n};
+    const bool prof = p->prof && kind == mk::KIND_MTTKRP;
+    if (prof) {
+        ev.a = take_event(p);
+        ev.b = take_event(p);
+        if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
+    }
+    HIPCHK(p, launch_mttkrp_any(L.N, a, fdt == MTTKRP_BF16, c, kind, grid, s));
+    if (prof) {
+        if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
+        p->events.push_back(ev);
+    }
+    if (kind != mk::KIND_LOSS && p->nsplit[n] > 0) {
+        const int RL = std::min(256, next_pow2(L.R));
+        hipLaunchKernelGGL(carry_fixup_kernel, dim3((unsigned)p->nsplit[n]), dim3(256), 0, s,
+                           p->split(n), a.carry, out, L.R, RL);
+        HIPCHK(p, hipGetLastError());
+    }
+    if (fuse) {
+        p->buf ^= 1;
+        p->cur = (n + 1) % L.N;
+    }
+    return MTTKRP_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char *mttkrp_status_str(mttkrp_status st)
+{
+    switch (st) {
+    case MTTKRP_OK: return "ok";
+    case MTTKRP_EINVAL: return "invalid argument";
+    case MTTKRP_ERANGE: return "coordinate out of range";
+    case MTTKRP_ENOMEM: return "workspace too small";
+    case MTTKRP_ESTATE: return "tensor is in another mode's layout";
+    case MTTKRP_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *mttkrp_last_error(mttkrp_plan_t p)
+{
+    return p ? p->err.c_str() : g_last_error.c_str();
+}
+
+mttkrp_status mttkrp_plan_workspace(int nmodes, const int64_t *dims, int64_t nnz, int rank,
+                                    const mttkrp_plan_opts *opts, size_t *bytes)
+{
+    if (!bytes) return fail(nullptr, MTTKRP_EINVAL, "bytes is NULL");
+    Layout L;
+    std::string why;
+    mttkrp_status st = compute_layout(nmodes, dims, nnz, rank, opts, &L, &why);
+    if (st != MTTKRP_OK) return fail(nullptr, st, why);
+    *bytes = L.total;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const int32_t *d_idx,
+                          const float *d_vals, int rank, const mttkrp_plan_opts *opts,
+                          void *d_workspace, size_t ws_bytes, void *stream, mttkrp_plan_t *out)
+{
+    if (!out) return fail(nullptr, MTTKRP_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    std::string why;
+    mttkrp_status st = compute_layout(nmodes, dims, nnz, rank, opts, &L, &why);
+    if (st != MTTKRP_OK) return fail(nullptr, st, why);
+    if (!d_workspace) return fail(nullptr, MTTKRP_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
+        return fail(nullptr, MTTKRP_EINVAL, "workspace must be 256-byte aligned");
+    if (nnz > 0 && (!d_idx || !d_vals)) return fail(nullptr, MTTKRP_EINVAL, "idx/vals is NULL");
+    if (ws_bytes < L.total)
+        return fail(nullptr, MTTKRP_ENOMEM,
+                    "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                        std::to_string(L.total));
+    mttkrp_plan_t p = new (std::nothrow) mttkrp_plan_s();
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "host allocation failed");
+    p->L = L;
+    p->ws = reinterpret_cast<char *>(d_workspace);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int N = L.N;
+    auto bail = [&](mttkrp_status e) {
+        g_last_error = p->err;
+        delete p;
+        return e;
+    };
+    if (nnz == 0) {
+        for (int n = 0; n < N; ++n) {
+            if (hipMemsetAsync(p->rp(n), 0, (L.dims[n] + 1) * 4, s) != hipSuccess)
+                return bail(fail(p, MTTKRP_EHIP, "hipMemsetAsync failed"));
+            p->nempty[n] = L.dims[n];
+        }
+        if (hipMemsetAsync(p->xx(), 0, 8, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "initialisation failed"));
+        *out = p;
+        return MTTKRP_OK;
+    }
+    // 1. index validation
+    int32_t *err = p->rt<int32_t>(L.ps_err);
+    plan::Dims8 d8;
+    for (int n = 0; n < 8; ++n) d8.d[n] = n < N ? (int32_t)L.dims[n] : 0;
+    int32_t herr = 0;
+    if (hipMemsetAsync(err, 0, 4, s) != hipSuccess) return bail(fail(p, MTTKRP_EHIP, "memset"));
+    hipLaunchKernelGGL(plan::validate_kernel, dim3(grid_for(nnz * N)), dim3(256), 0, s, d_idx, N,
+                       nnz, d8, err);
+    if (hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(p, MTTKRP_EHIP, std::string("validation: ") +
+                                             hipGetErrorString(hipGetLastError())));
+    if (herr) return bail(fail(p, MTTKRP_ERANGE, "a coordinate is outside [0, I_n)"));
+
+    int32_t *kb[2] = {p->rt<int32_t>(L.ps_k0), p->rt<int32_t>(L.ps_k1)};
+    int32_t *vb[2] = {p->rt<int32_t>(L.ps_v0), p->rt<int32_t>(L.ps_v1)};
+    int32_t *ob[2] = {p->rt<int32_t>(L.ps_o0), p->rt<int32_t>(L.ps_o1)};
+    const unsigned gg = grid_for(nnz);
+    // 2. L_0: stable LSD sort of input positions by c_1, c_2, ..., c_{N-1}, c_0
+    const int32_t *src = nullptr;
+    for (int t = 1; t <= N; ++t) {
+        const int w = t % N;
+        hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + w * nnz,
+                           src, nnz, kb[0], vb[0], 0);
+        int which = 0;
+        st = radix_sort(p, kb[0], vb[0], kb[1], vb[1], nnz, key_bits(L.dims[w]), s, &which);
+        if (st != MTTKRP_OK) return bail(st);
+        // keep the permutation in ob[0]
+        if (hipMemcpyAsync(ob[0], vb[which], nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "copy"));
+        src = ob[0];
+    }
+    if (launch_pack_any(N, d_idx, d_vals, ob[0], nnz, p->rec(0), s) != hipSuccess)
+        return bail(fail(p, MTTKRP_EHIP, "pack launch"));
+    // 3. per mode: row pointers of L_n; P_n by a stable sort of L_n by c_{n+1}
+    int oc = 0;
+    for (int n = 0; n < N; ++n) {
+        const int nx = (n + 1) % N;
+        hipLaunchKernelGGL(plan::row_ptr_kernel, dim3(grid_for(nnz + 1)), dim3(256), 0, s,
+                           d_idx + n * nnz, ob[oc], nnz, (int32_t)L.dims[n], p->rp(n));
+        hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + nx * nnz,
+                           ob[oc], nnz, kb[0], vb[0], 1);
+        int which = 0;
+        st = radix_sort(p, kb[0], vb[0], kb[1], vb[1], nnz, key_bits(L.dims[nx]), s, &which);
+        if (st != MTTKRP_OK) return bail(st);
+        hipLaunchKernelGGL(plan::invert_kernel, dim3(gg), dim3(256), 0, s, vb[which], nnz,
+                           p->perm(n), ob[oc], ob[oc ^ 1]);
+        if (hipGetLastError() != hipSuccess) return bail(fail(p, MTTKRP_EHIP, "plan kernels"));
+        oc ^= 1;
+    }
+    // ||X||^2 for the fit
+    {
+        const int nb = 1024;
+        double *part = p->rt<double>(L.rt_partial);   // sort buffers are free now
+        if (hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "plan sync"));
+        hipLaunchKernelGGL(als::sumsq_partial, dim3(nb), dim3(256), 0, s, p->rec(0), nnz, N + 1,
+                           part);
+        hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)nb, p->xx());
+    }
+    // 4. host partition tables
+    std::vector<int32_t> rp, shards, order, split, bins;
+    for (int n = 0; n < N; ++n) {
+        rp.resize(L.dims[n] + 1);
+        if (hipMemcpyAsync(rp.data(), p->rp(n), rp.size() * 4, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "row pointer copy"));
+        build_tables(L, n, rp, shards, order, split, bins, &p->nempty[n]);
+        p->nshards[n] = (int64_t)shards.size() / 3;
+        p->nsplit[n] = (int64_t)split.size() / 4;
+        if (p->nshards[n] > L.maxS[n]) return bail(fail(p, MTTKRP_EINVAL, "shard bound"));
+        if (hipMemcpyAsync(p->sh(n), shards.data(), shards.size() * 4, hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipMemcpyAsync(p->ord(n), order.data(), order.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            (!split.empty() && hipMemcpyAsync(p->split(n), split.data(), split.size() * 4,
+                                              hipMemcpyHostToDevice, s) != hipSuccess) ||
+            hipMemcpyAsync(p->lpt(n), bins.data(), bins.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "table upload"));
+    }
+    if (hipMemsetAsync(p->ridge(), 0, 8, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(p, MTTKRP_EHIP, "plan finish"));
+    p->cur = 0;
+    p->buf = 0;
+    *out = p;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_plan_destroy(mttkrp_plan_t p)
+{
+    if (!p) return MTTKRP_EINVAL;
+    for (auto &e : p->events) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+    }
+    for (auto e : p->pool) (void)hipEventDestroy(e);
+    delete p;
+    return MTTKRP_OK;
+}
+
+mttkrp_status remap(mttkrp_plan_t p, int to_mode, void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    if (to_mode < 0 || to_mode >= p->L.N) return fail(p, MTTKRP_EINVAL, "bad mode");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    while (p->cur != to_mode) {
+        mttkrp_status st = remap_step(p, s);
+        if (st != MTTKRP_OK) return st;
+    }
+    return MTTKRP_OK;
+}
+
+static mttkrp_status reach(mttkrp_plan_t p, int mode, hipStream_t s)
+{
+    if (p->cur == mode) return MTTKRP_OK;
+    if (p->L.flags & MTTKRP_NO_IMPLICIT_REMAP)
+        return fail(p, MTTKRP_ESTATE,
+                    "tensor is in layout " + std::to_string(p->cur) + ", not " +
+                        std::to_string(mode));
+    while (p->cur != mode) {
+        mttkrp_status st = remap_step(p, s);
+        if (st != MTTKRP_OK) return st;
+    }
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_mode(mttkrp_plan_t p, int mode, const void *const *d_factors,
+                          mttkrp_dtype fdt, float *d_out, int fuse_remap, void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    if (mode < 0 || mode >= p->L.N) return fail(p, MTTKRP_EINVAL, "bad mode");
+    if (!d_out) return fail(p, MTTKRP_EINVAL, "out is NULL");
+    mttkrp_status st = check_factors(p, d_factors, 1, mode, fdt);
+    if (st != MTTKRP_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    st = reach(p, mode, s);
+    if (st != MTTKRP_OK) return st;
+    return run_pass(p, d_factors, fdt, d_out, fuse_remap != 0, mk::KIND_MTTKRP, nullptr, s);
+}
+
+mttkrp_status mttkrp_all_modes(mttkrp_plan_t p, const void *const *d_factors, mttkrp_dtype fdt,
+                               float *const *d_out, void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    if (!d_out) return fail(p, MTTKRP_EINVAL, "out is NULL");
+    for (int n = 0; n < p->L.N; ++n)
+        if (!d_out[n]) return fail(p, MTTKRP_EINVAL, "out pointer is NULL");
+    mttkrp_status st = check_factors(p, d_factors, 0, -1, fdt);
+    if (st != MTTKRP_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t saved = p->L.flags;
+    p->L.flags &= ~MTTKRP_NO_IMPLICIT_REMAP;
+    st = reach(p, 0, s);
+    p->L.flags = saved;
+    if (st != MTTKRP_OK) return st;
+    for (int n = 0; n < p->L.N; ++n) {
+        st = run_pass(p, d_factors, fdt, d_out[n], true, mk::KIND_MTTKRP, nullptr, s);
+        if (st != MTTKRP_OK) return st;
+    }
+    return MTTKRP_OK;
+}
+
+mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp_dtype fdt,
+                           double *d_loss, float *const *d_grads, const double *d_grad_scale,
+                           void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    mttkrp_status st = check_factors(p, d_factors, 0, -1, fdt);
+    if (st != MTTKRP_OK) return st;
+    if (d_grads)
+        for (int k = 0; k < p->L.N; ++k)
+            if (!d_grads[k]) return fail(p, MTTKRP_EINVAL, "gradient pointer is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    if (d_loss) {
+        if (L.nnz == 0) {
+            HIPCHK(p, hipMemsetAsync(d_loss, 0, 8, s));
+        } else {
+            st = run_pass(p, d_factors, fdt, nullptr, false, mk::KIND_LOSS, nullptr, s);
+            if (st != MTTKRP_OK) return st;
+            hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s,
+                               p->rt<double>(L.rt_partial), p->nshards[p->cur], d_loss);
+            HIPCHK(p, hipGetLastError());
+        }
+    }
+    if (d_grads) {
+        const int start = p->cur;
+        for (int t = 0; t < L.N; ++t) {
+            const int k = (start + t) % L.N;
+            st = run_pass(p, d_factors, fdt, d_grads[k], true, mk::KIND_RESID, d_grad_scale, s);
+            if (st != MTTKRP_OK) return st;
+        }
+    }
+    return MTTKRP_OK;
+}
+
+mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                           float *d_mbuf, double *d_lambda, double *d_fit, void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    mttkrp_status st = check_factors(p, (const void *const *)d_factors, 0, -1, fdt);
+    if (st != MTTKRP_OK) return st;
+    if (!d_mbuf || !d_lambda) return fail(p, MTTKRP_EINVAL, "mbuf/lambda is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    const int N = L.N, R = L.R;
+    const bool bf = fdt == MTTKRP_BF16;
+    double *G = p->rt<double>(L.rt_G);
+    double *gpart = p->rt<double>(L.rt_gpart);
+    const int tiles = (R + als::GRAM_TILE - 1) / als::GRAM_TILE;
+    const int gb = std::max(1, GRAM_TARGET_BLOCKS / (tiles * tiles));
+    auto gram = [&](int w) -> mttkrp_status {
+        const int64_t I = L.dims[w];
+        const int64_t chunk = (I + gb - 1) / gb;
+        const dim3 grid(gb, tiles, tiles), blk(als::GRAM_TILE, als::GRAM_TILE);
+        if (bf)
+            hipLaunchKernelGGL(als::gram_partial<uint16_t>, grid, blk, 0, s,
+                               (const uint16_t *)d_factors[w], I, R, chunk, gpart);
+        else
+            hipLaunchKernelGGL(als::gram_partial<float>, grid, blk, 0, s,
+                               (const float *)d_factors[w], I, R, chunk, gpart);
+        hipLaunchKernelGGL(als::gram_reduce, dim3(grid_for(R * R)), dim3(256), 0, s, gpart, gb, R,
+                           G + (int64_t)w * R * R);
+        HIPCHK(p, hipGetLastError());
+        return MTTKRP_OK;
+    };
+    HIPCHK(p, hipMemsetAsync(p->ridge(), 0, 8, s));
+    const uint32_t saved = p->L.flags;
+    p->L.flags &= ~MTTKRP_NO_IMPLICIT_REMAP;
+    st = reach(p, 0, s);
+    p->L.flags = saved;
+    if (st != MTTKRP_OK) return st;
+    for (int w = 0; w < N; ++w)
+        if ((st = gram(w)) != MTTKRP_OK) return st;
+    const int RT = std::min(256, next_pow2(R));
+    double *colsq = p->rt<double>(L.rt_colsq);
+    for (int n = 0; n < N; ++n) {
+        st = run_pass(p, (const void *const *)d_factors, fdt, d_mbuf, true, mk::KIND_MTTKRP,
+                      nullptr, s);
+        if (st != MTTKRP_OK) return st;
+        hipLaunchKernelGGL(als::chol_inverse, dim3(1), dim3(256), 0, s, G, N, n, R,
+                           p->rt<double>(L.rt_L), p->rt<double>(L.rt_Linv), p->rt<double>(L.rt_W),
+                           p->ridge(), p->fail());
+        const int64_t I = L.dims[n];
+        const double *W = p->rt<double>(L.rt_W);
+        if (bf) {
+            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+                               d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (uint16_t *)d_factors[n]);
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(1), dim3(256), 0, s, colsq,
+                               als::APPLY_BLOCKS, R, d_lambda);
+            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+                               d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (uint16_t *)d_factors[n]);
+        } else {
+            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+                               d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (float *)d_factors[n]);
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(1), dim3(256), 0, s, colsq,
+                               als::APPLY_BLOCKS, R, d_lambda);
+            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+                               d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (float *)d_factors[n]);
+        }
+        HIPCHK(p, hipGetLastError());
+        if ((st = gram(n)) != MTTKRP_OK) return st;
+    }
+    if (d_fit) {
+        const int n = N - 1;
+        double *inner = colsq;
+        if (bf)
+            hipLaunchKernelGGL(als::inner_partial<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0,
+                               s, d_mbuf, (const uint16_t *)d_factors[n], L.dims[n], R, RT, inner);
+        else
+            hipLaunchKernelGGL(als::inner_partial<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+                               d_mbuf, (const float *)d_factors[n], L.dims[n], R, RT, inner);
+        hipLaunchKernelGGL(als::fit_kernel, dim3(1), dim3(256), 0, s, inner, als::APPLY_BLOCKS, G,
+                           N, d_lambda, R, p->xx(), d_fit);
+        HIPCHK(p, hipGetLastError());
+    }
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst, size_t bytes,
+                                void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    if (mode < 0 || mode >= p->L.N) return fail(p, MTTKRP_EINVAL, "bad mode");
+    int64_t need = 0;
+    const Layout &L = p->L;
+    const void *src = nullptr;
+    switch (what) {
+    case MTTKRP_Q_LAYOUT: need = L.nnz * (L.N + 1) * 4; src = p->rec(p->buf); break;
+    case MTTKRP_Q_PERM: need = L.nnz * 4; src = p->perm(mode); break;
+    case MTTKRP_Q_ROW_PTR: need = (L.dims[mode] + 1) * 4; src = p->rp(mode); break;
+    case MTTKRP_Q_SHARDS: need = p->nshards[mode] * 12; src = p->sh(mode); break;
+    case MTTKRP_Q_LPT: need = L.k[mode] * 4; src = p->lpt(mode); break;
+    default: return fail(p, MTTKRP_EINVAL, "bad query");
+    }
+    if (!dst || bytes < (size_t)need) return fail(p, MTTKRP_EINVAL, "destination too small");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (need > 0) HIPCHK(p, hipMemcpyAsync(dst, src, need, hipMemcpyDefault, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *value)
+{
+    if (!p || !value) return fail(p, MTTKRP_EINVAL, "NULL argument");
+    const Layout &L = p->L;
+    auto mode_ok = [&]() { return mode >= 0 && mode < L.N; };
+    switch (what) {
+    case MTTKRP_INFO_CUR_MODE: *value = p->cur; return MTTKRP_OK;
+    case MTTKRP_INFO_G: *value = L.g; return MTTKRP_OK;
+    case MTTKRP_INFO_NSHARDS:
+    case MTTKRP_INFO_NSUPER:
+    case MTTKRP_INFO_NSPLIT:
+    case MTTKRP_INFO_M:
+        if (!mode_ok()) return fail(p, MTTKRP_EINVAL, "bad mode");
+        *value = what == MTTKRP_INFO_NSHARDS ? p->nshards[mode]
+                 : what == MTTKRP_INFO_NSUPER ? L.k[mode]
+                 : what == MTTKRP_INFO_NSPLIT ? p->nsplit[mode]
+                                              : L.m[mode];
+        return MTTKRP_OK;
+    case MTTKRP_INFO_RIDGE: {
+        int32_t h = 0;
+        HIPCHK(p, hipDeviceSynchronize());
+        HIPCHK(p, hipMemcpy(&h, p->ridge(), 4, hipMemcpyDeviceToHost));
+        *value = h;
+        return MTTKRP_OK;
+    }
+    }
+    return fail(p, MTTKRP_EINVAL, "bad info key");
+}
+
+mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    p->prof = enable != 0;
+    return MTTKRP_OK;
+}
+
+mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms, int64_t *launches)
+{
+    if (!p || !ms || !launches) return fail(p, MTTKRP_EINVAL, "NULL argument");
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &e : p->events) {
+        if (e.a && e.b && (mode < 0 || e.mode == mode)) {
+            HIPCHK(p, hipEventSynchronize(e.b));
+            float t = 0.0f;
+            HIPCHK(p, hipEventElapsedTime(&t, e.a, e.b));
+            tot += t;
+            ++cnt;
+        }
+    }
+    for (auto &e : p->events) {
+        if (e.a) p->pool.push_back(e.a);
+        if (e.b) p->pool.push_back(e.b);
+    }
+    p->events.clear();
+    *ms = tot;
+    *launches = cnt;
+    return MTTKRP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+// Integer preprocessing kernels (plan): index validation, stable LSD radix
+// sort of positions by one coordinate, permutation inversion, row pointers,
+// packing of the mode-0 layout.  No global atomics: per-tile histograms,
+// a device-wide exclusive scan, and an order-preserving per-tile scatter.
+#pragma once
+#include "common.hpp"
+
+namespace plan {
+
+constexpr int TILE = 4096;          // items per radix tile
+constexpr int SCAN_CHUNK = 1024;    // items per scan block (256 threads x 4)
+
+// err[0] = 1 if any coordinate of mode n is outside [0, dims[n]).
+struct Dims8 { int32_t d[8]; };
+
+__global__ void validate_kernel(const int32_t *__restrict__ idx, int nmodes, int64_t nnz,
+                                Dims8 dims, int32_t *__restrict__ err)
+{
+    int64_t total = nnz * nmodes;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int n = (int)(t / nnz);
+        int32_t c = idx[t];
+        if (c < 0 || c >= dims.d[n]) err[0] = 1;   // benign same-value race
+    }
+}
+
+// keys[j] = coord[src[j]] (src == nullptr: identity); vals[j] = j when
+// iota is set, else src[j].
+__global__ void gather_keys_kernel(const int32_t *__restrict__ coord,
+                                   const int32_t *__restrict__ src, int64_t n,
+                                   int32_t *__restrict__ keys, int32_t *__restrict__ vals,
+                                   int iota)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = src ? src[j] : (int32_t)j;
+        keys[j] = coord[s];
+        vals[j] = iota ? (int32_t)j : s;
+    }
+}
+
+// Per-tile digit histogram, digit-major: hist[d * ntiles + tile].
+__global__ __launch_bounds__(256) void radix_upsweep(const int32_t *__restrict__ keys,
+                                                     int64_t n, int shift,
+                                                     int32_t *__restrict__ hist, int ntiles)
+{
+    __shared__ int32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * TILE;
+    for (int k = threadIdx.x; k < TILE; k += 256) {
+        int64_t j = base + k;
+        if (j < n) atomicAdd(&cnt[(keys[j] >> shift) & 255], 1);   // LDS atomic
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan, three phases over chunks of SCAN_CHUNK.
+__device__ __forceinline__ int32_t block_excl_scan256(int32_t v, int32_t *sh, int32_t *total)
+{
+    // inclusive scan within waves, then across the 4 waves
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t t = __shfl_up(x, d);
+        if (lane >= d) x += t;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int32_t off = 0;
+    for (int k = 0; k < w; ++k) off += sh[k];
+    *total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce(const int32_t *__restrict__ in, int64_t n,
+                                                   int32_t *__restrict__ sums)
+{
+    __shared__ int32_t sh[4];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int32_t v = 0;
+    for (int k = 0; k < 4; ++k) {
+        int64_t j = base + threadIdx.x * 4 + k;
+        if (j < n) v += in[j];
+    }
+    int32_t tot;
+    block_excl_scan256(v, sh, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of `n` chunk sums in place (sequential over
+// groups of 1024).
+__global__ __launch_bounds__(256) void scan_sums(int32_t *__restrict__ sums, int64_t n)
+{
+    __shared__ int32_t sh[4];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n; base += SCAN_CHUNK) {
+        int32_t v[4], s = 0;
+        for (int k = 0; k < 4; ++k) {
+            int64_t j = base + threadIdx.x * 4 + k;
+            v[k] = (j < n) ? sums[j] : 0;
+            s += v[k];
+        }
+        int32_t tot;
+        int32_t ex = block_excl_scan256(s, sh, &tot);
+        int32_t run = carry + ex;
+        for (int k = 0; k < 4; ++k) {
+            int64_t j = base + threadIdx.x * 4 + k;
+            if (j < n) sums[j] = run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_apply(const int32_t *__restrict__ in, int64_t n,
+                                                  const int32_t *__restrict__ sums,
+                                                  int32_t *__restrict__ out)
+{
+    __shared__ int32_t sh[4];
+    int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+    int32_t v[4], s = 0;
+    for (int k = 0; k < 4; ++k) {
+        int64_t j = base + threadIdx.x * 4 + k;
+        v[k] = (j < n) ? in[j] : 0;
+        s += v[k];
+    }
+    int32_t tot;
+    int32_t run = sums[blockIdx.x] + block_excl_scan256(s, sh, &tot);
+    for (int k = 0; k < 4; ++k) {
+        int64_t j = base + threadIdx.x * 4 + k;
+        if (j < n) out[j] = run;
+        run += v[k];
+    }
+}
+
+// Stable scatter of one tile by one wave, 64 rounds of 64 consecutive items:
+// items with equal digits keep their order (rank via ballot matching).
+__global__ __launch_bounds__(64) void radix_scatter(const int32_t *__restrict__ kin,
+                                                   const int32_t *__restrict__ vin, int64_t n,
+                                                   int shift, const int32_t *__restrict__ offs,
+                                                   int ntiles, int32_t *__restrict__ kout,
+                                                   int32_t *__restrict__ vout)
+{
+    __shared__ int32_t base[256];
+    const int lane = threadIdx.x;
+    for (int d = lane; d < 256; d += 64) base[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t t0 = (int64_t)blockIdx.x * TILE;
+    for (int rnd = 0; rnd < TILE / 64; ++rnd) {
+        int64_t j = t0 + rnd * 64 + lane;
+        bool ok = j < n;
+        int32_t k = ok ? kin[j] : 0;
+        int32_t v = ok ? vin[j] : 0;
+        int dg = (k >> shift) & 255;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bits = __ballot((dg >> b) & 1);
+            peers &= ((dg >> b) & 1) ? bits : ~bits;
+        }
+        int rank = __popcll(peers & lt);
+        int pos = 0;
+        if (ok) pos = base[dg] + rank;
+        __syncthreads();
+        // the highest lane of each digit group advances the running base
+        bool leader = ok && ((peers >> lane) == 1ull);
+        if (leader) base[dg] += __popcll(peers);
+        __syncthreads();
+        if (ok) {
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        if (t0 + rnd * 64 + 64 >= n) break;
+    }
+}
+
+// P[q[t]] = t ; onew[t] = oold[q[t]]   (q = positions of L_n in L_{n+1} order)
+__global__ void invert_kernel(const int32_t *__restrict__ q, int64_t n, int32_t *__restrict__ P,
+                              const int32_t *__restrict__ oold, int32_t *__restrict__ onew)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t s = q[t];
+        P[s] = (int32_t)t;
+        onew[t] = oold[s];
+    }
+}
+
+// Row pointers of a layout sorted by coordinate c = coord[o[j]]:
+// row_ptr[r] = first j with c >= r; every entry written exactly once.
+__global__ void row_ptr_kernel(const int32_t *__restrict__ coord, const int32_t *__restrict__ o,
+                               int64_t n, int32_t I, int32_t *__restrict__ row_ptr)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int32_t cur = (j < n) ? coord[o[j]] : I;
+        int32_t prev = (j > 0) ? coord[o[j - 1]] : -1;
+        for (int32_t r = prev + 1; r <= cur; ++r) row_ptr[r] = (int32_t)j;
+    }
+}
+
+}  // namespace plan

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU needed): every symbol the header
+declares is exported, and argument errors are reported as status codes
+before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2309_09131_amd import _abi, build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        build.build_lib(force=False)
+    return _abi.load()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "mttkrp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(",
+                                 src, flags=re.M)))
+
+
+def test_header_symbols_exported(lib):
+    names = header_functions()
+    assert len(names) >= 14, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_abi.SYMBOLS)
+
+
+def test_workspace_argument_errors(lib):
+    ok = _abi.mttkrp_plan_workspace(3, (10, 20, 30), 1000, 16)
+    assert ok > 1000 * 16 * 2
+    for args in [(1, (10,), 5, 4), (9, (2,) * 9, 5, 4), (3, (10, 20, 30), 5, 0),
+                 (3, (10, 20, 30), 5, 257), (3, (10, 0, 30), 5, 4),
+                 (3, (10, 20, 30), -1, 4), (3, (10, 20, 30), 1 << 31, 4)]:
+        with pytest.raises(_abi.MttkrpError) as ei:
+            _abi.mttkrp_plan_workspace(*args)
+        assert ei.value.status == _abi.EINVAL, args
+    with pytest.raises(_abi.MttkrpError):
+        _abi.mttkrp_plan_workspace(3, (10, 20, 30), 5, 4, _abi.make_opts(g=-1))
+
+
+def test_plan_argument_errors_before_device_work(lib):
+    dims = (10, 20, 30)
+    need = _abi.mttkrp_plan_workspace(3, dims, 100, 8)
+    # NULL workspace, misaligned workspace, NULL inputs, small workspace
+    with pytest.raises(_abi.MttkrpError) as ei:
+        _abi.mttkrp_plan(3, dims, 100, 4096, 8192, 8, None, 0, need)
+    assert ei.value.status == _abi.EINVAL
+    with pytest.raises(_abi.MttkrpError) as ei:
+        _abi.mttkrp_plan(3, dims, 100, 4096, 8192, 8, None, 4096 + 8, need)
+    assert ei.value.status == _abi.EINVAL
+    with pytest.raises(_abi.MttkrpError) as ei:
+        _abi.mttkrp_plan(3, dims, 100, 0, 8192, 8, None, 4096, need)
+    assert ei.value.status == _abi.EINVAL
+    with pytest.raises(_abi.MttkrpError) as ei:
+        _abi.mttkrp_plan(3, dims, 100, 4096, 8192, 8, None, 4096, need - 1)
+    assert ei.value.status == _abi.ENOMEM
+    assert "needs" in _abi.mttkrp_last_error(None)
+
+
+def test_calls_on_null_plan_are_einval(lib):
+    for fn, args in [(lib.mttkrp_mode, (None, 0, None, 0, None, 1, None)),
+                     (lib.mttkrp_all_modes, (None, None, 0, None, None)),
+                     (lib.remap, (None, 0, None)),
+                     (lib.cp_loss_grad, (None, None, 0, None, None, None, None)),
+                     (lib.cp_als_sweep, (None, None, 0, None, None, None, None)),
+                     (lib.mttkrp_plan_destroy, (None,))]:
+        assert fn(*args) == _abi.EINVAL
+    assert lib.mttkrp_status_str(_abi.ESTATE).decode().startswith("tensor")
+
+
+def test_status_strings(lib):
+    for st in range(6):
+        assert len(_abi.mttkrp_status_str(st)) > 0

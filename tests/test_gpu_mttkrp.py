@@ -1,0 +1,172 @@
+"""GPU parity of the plan, remap and per-mode MTTKRP against the FP64 oracle.
+
+Integer work (layouts, remap targets, row pointers, shard tables, schedule)
+must match bit for bit; floating point within 1e-5 (FP32) / 2e-2 (BF16),
+normwise and elementwise relative to the |.|-sum M^abs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (BF16_TOL, FP32_TOL, _abi, bf16_round, check_close,
+                        dev, make_plan, oracle, oracle_layout_records, say,
+                        to_dev)
+from paper_2309_09131_amd import synthetic as syn
+from paper_2309_09131_amd.api import Plan
+
+pytestmark = pytest.mark.gpu
+
+PLAN_CASES = [
+    # dims, nnz, R, seed, distinct, zipf, g
+    ((60, 50, 40), 3000, 16, 1, True, 0.0, 64),
+    ((7, 5, 6), 150, 4, 2, False, 0.0, 16),          # duplicates
+    ((40, 3, 30, 5), 2500, 8, 3, True, 1.2, 100),
+    ((9, 2, 11, 3, 4), 900, 5, 4, False, 0.0, 32),
+    ((300, 200), 5000, 3, 5, True, 1.1, 128),
+    ((1, 40, 30), 600, 2, 6, True, 0.0, 50),          # I_0 = 1
+]
+
+
+@pytest.mark.parametrize("case", PLAN_CASES)
+def test_plan_tables_bit_exact(case):
+    dims, nnz, R, seed, distinct, zipf, g = case
+    say("plan case", case)
+    t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
+    p, _ = make_plan(t, g=g, workers=4)
+    l0 = oracle.canonical_order(t.idx)
+    layouts, perm, rps = oracle.remap_replay(dims, t.idx, l0)
+    got = p.query(_abi.Q_LAYOUT)
+    assert np.array_equal(got, oracle_layout_records(t, layouts[0]))
+    N = len(dims)
+    for n in range(N):
+        assert np.array_equal(p.query(_abi.Q_PERM, n), perm[n]), n
+        assert np.array_equal(p.query(_abi.Q_ROW_PTR, n), rps[n]), n
+        m = p.info(_abi.INFO_M, n)
+        sh = oracle.shards(dims[n], rps[n], m, g)
+        tab = p.query(_abi.Q_SHARDS, n)
+        assert np.array_equal(tab[:, 0], sh["start"])
+        assert np.array_equal(tab[:, 1], sh["len"])
+        assert np.array_equal(tab[:, 2], sh["ss"])
+        bins, _ = oracle.lpt(sh["ss_shards"], 4)
+        assert np.array_equal(p.query(_abi.Q_LPT, n), bins)
+    # standalone remap walks the oracle's layouts and returns to L_0
+    for n in range(1, N + 1):
+        p.remap(n % N)
+        assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                              oracle_layout_records(t, layouts[n])), n
+
+
+MTT_CASES = [
+    # dims, nnz, R, seed, distinct, zipf, g, factor dtype
+    ((60, 50, 40), 3000, 16, 11, True, 0.0, 64),
+    ((60, 50, 40), 3000, 32, 12, True, 1.2, 64),
+    ((30, 20, 10), 1500, 64, 13, False, 0.0, 100),
+    ((50, 40, 30), 2000, 17, 14, True, 0.0, 64),      # strided lanes
+    ((20, 30, 25), 800, 1, 15, True, 0.0, 32),
+    ((20, 30, 25), 800, 256, 16, True, 0.0, 128),
+    ((40, 3, 30, 5), 2500, 8, 17, True, 1.2, 100),
+    ((9, 2, 11, 3, 4), 900, 20, 18, False, 0.0, 32),
+    ((300, 200), 5000, 12, 19, True, 1.1, 128),
+    ((3, 2, 2, 3, 2, 2, 3, 2), 700, 16, 20, False, 0.0, 50),   # N = 8
+    ((2000, 30, 20), 500, 16, 21, True, 0.0, 64),     # many empty rows
+    ((50, 40, 30), 37, 16, 22, True, 0.0, 1024),      # nnz < 64
+    ((4, 500, 300), 20000, 16, 23, True, 1.5, 64),    # rows over many shards
+]
+
+
+def _oracle_all(t, facs64):
+    return [oracle.mttkrp(t.dims, t.idx, t.vals, facs64, n, with_abs=True)
+            for n in range(len(t.dims))]
+
+
+@pytest.mark.parametrize("case", MTT_CASES)
+def test_mttkrp_all_modes_fp32(case):
+    dims, nnz, R, seed, distinct, zipf, g = case
+    say("mttkrp fp32 case", case)
+    t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
+    p, facs = make_plan(t, g=g)
+    outs = p.mttkrp_all_modes(facs)
+    torch.cuda.synchronize()
+    assert p.cur_mode == 0
+    ref = _oracle_all(t, t.factors)
+    for n in range(len(dims)):
+        check_close(outs[n].cpu().numpy(), ref[n][0], ref[n][1], FP32_TOL, f"mode {n}")
+    # deterministic: a second sweep is bit-identical
+    outs2 = p.mttkrp_all_modes(facs)
+    for a, b in zip(outs, outs2):
+        assert torch.equal(a, b)
+    # the layout is back in L_0 and byte-identical to the oracle's
+    assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                          oracle_layout_records(t, oracle.canonical_order(t.idx)))
+
+
+@pytest.mark.parametrize("case", [c for c in MTT_CASES if c[2] % 8 == 0 or c[2] in (1, 17, 20, 12)])
+def test_mttkrp_bf16_factors(case):
+    dims, nnz, R, seed, distinct, zipf, g = case
+    say("mttkrp bf16 case", case)
+    t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
+    idx, vals, facs = to_dev(t, torch.bfloat16)
+    p = Plan(idx, vals, dims, R, g=g)
+    outs = p.mttkrp_all_modes(facs)
+    ref32 = _oracle_all(t, t.factors)                        # includes storage error
+    refb = _oracle_all(t, [bf16_round(f) for f in t.factors])  # accumulation only
+    for n in range(len(dims)):
+        got = outs[n].cpu().numpy()
+        check_close(got, ref32[n][0], ref32[n][1], BF16_TOL, f"bf16 vs fp32 mode {n}")
+        check_close(got, refb[n][0], refb[n][1], FP32_TOL, f"bf16 vs bf16-oracle {n}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_integer_inputs_bit_exact(dtype):
+    """Integer values in [1,4], factors in [-2,2]: every partial sum is an
+    integer below 2^24, so any summation order gives the exact result."""
+    for dims, R, g in [((40, 30, 20), 16, 64), ((12, 9, 7, 5), 32, 50),
+                       ((30, 25), 24, 40)]:
+        t = syn.random_tensor(dims, 1500, R, 31, distinct=False, int_values=True)
+        idx, vals, facs = to_dev(t, dtype)
+        p = Plan(idx, vals, dims, R, g=g)
+        outs = p.mttkrp_all_modes(facs)
+        for n in range(len(dims)):
+            ref = oracle.mttkrp(dims, t.idx, t.vals, t.factors, n)
+            assert np.array_equal(outs[n].cpu().numpy().astype(np.float64), ref), (dims, n)
+
+
+def test_single_mode_fused_and_unfused_and_state():
+    t = syn.random_tensor((80, 60, 40, 30), 5000, 16, 41, zipf_s=1.1)
+    p, facs = make_plan(t, g=128, flags=_abi.NO_IMPLICIT_REMAP)
+    ref = _oracle_all(t, t.factors)
+    out = p.mttkrp_mode(0, facs, fuse_remap=False)
+    check_close(out.cpu().numpy(), ref[0][0], ref[0][1], FP32_TOL, "unfused mode 0")
+    assert p.cur_mode == 0
+    with pytest.raises(_abi.MttkrpError) as ei:
+        p.mttkrp_mode(2, facs)
+    assert ei.value.status == _abi.ESTATE
+    for n in range(4):
+        out = p.mttkrp_mode(n, facs, fuse_remap=True)
+        check_close(out.cpu().numpy(), ref[n][0], ref[n][1], FP32_TOL, f"fused {n}")
+    assert p.cur_mode == 0
+    # implicit remap when allowed
+    q, facs2 = make_plan(t, g=128)
+    out = q.mttkrp_mode(3, facs2, fuse_remap=False)
+    assert q.cur_mode == 3
+    check_close(out.cpu().numpy(), ref[3][0], ref[3][1], FP32_TOL, "implicit")
+
+
+def test_out_of_range_index_is_erange():
+    d = dev()
+    idx = torch.tensor([[0, 1, 5], [0, 1, 2]], dtype=torch.int32, device=d)
+    vals = torch.ones(3, dtype=torch.float32, device=d)
+    with pytest.raises(_abi.MttkrpError) as ei:
+        Plan(idx, vals, (5, 3), 4)
+    assert ei.value.status == _abi.ERANGE
+
+
+def test_empty_tensor_gives_zero_outputs():
+    d = dev()
+    idx = torch.zeros((3, 0), dtype=torch.int32, device=d)
+    vals = torch.zeros(0, dtype=torch.float32, device=d)
+    p = Plan(idx, vals, (5, 4, 3), 8)
+    facs = [torch.randn(n, 8, device=d) for n in (5, 4, 3)]
+    outs = p.mttkrp_all_modes(facs)
+    for o in outs:
+        assert torch.count_nonzero(o) == 0
