@@ -195,7 +195,8 @@ mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *val
 /* Kernel timing with HIP events on the launch stream: when enabled, every
  * per-mode MTTKRP kernel launch is bracketed by events.  mttkrp_profile_read
  * synchronises, returns the summed milliseconds and launch count of that
- * kernel for `mode` (-1: all modes) since the last reset, and resets. */
+ * kernel for `mode` (-1: all modes) since the last reset, and resets the
+ * events it read. */
 mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable);
 mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms,
                                   int64_t *launches);

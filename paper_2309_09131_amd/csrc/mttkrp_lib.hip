@@ -930,11 +930,16 @@ mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms, int64_t
             ++cnt;
         }
     }
+    std::vector<ProfEvent> keep;
     for (auto &e : p->events) {
+        if (mode >= 0 && e.mode != mode) {
+            keep.push_back(e);
+            continue;
+        }
         if (e.a) p->pool.push_back(e.a);
         if (e.b) p->pool.push_back(e.b);
     }
-    p->events.clear();
+    p->events.swap(keep);
     *ms = tot;
     *launches = cnt;
     return MTTKRP_OK;

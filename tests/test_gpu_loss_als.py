@@ -1,0 +1,183 @@
+"""GPU parity of the sampled CP loss (forward, adjoint, autograd) and of the
+CP-ALS sweep against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (BF16_TOL, FP32_TOL, _abi, bf16_round, check_close,
+                        dev, oracle, say, to_dev)
+from paper_2309_09131_amd import synthetic as syn
+from paper_2309_09131_amd.api import Plan, cp_loss
+
+pytestmark = pytest.mark.gpu
+
+LOSS_CASES = [((60, 50, 40), 4000, 16, 51, 64), ((40, 3, 30, 5), 2500, 32, 52, 100),
+              ((200, 150, 100), 20000, 64, 53, 256), ((30, 25, 20), 1000, 17, 54, 64),
+              ((9, 2, 11, 3, 4), 900, 8, 55, 32)]
+
+
+def _loss_case(case):
+    dims, nnz, R, seed, g = case
+    t = syn.random_tensor(dims, nnz, R, seed, factors="uniform")
+    idx, vals, facs = to_dev(t)
+    return t, Plan(idx, vals, dims, R, g=g), facs
+
+
+def _grad_ref(t, facs64):
+    """Oracle gradient and an |.| scale: -2 * MTTKRP with values rho."""
+    N = len(t.dims)
+    m = np.zeros(t.nnz)
+    mabs = np.zeros(t.nnz)
+    for r in range(t.rank):
+        p = np.ones(t.nnz)
+        for n in range(N):
+            p = p * facs64[n][t.idx[n], r]
+        m += p
+        mabs += np.abs(p)
+    rho = t.vals.astype(np.float64) - m
+    refs = []
+    for k in range(N):
+        g, _ = oracle.mttkrp(t.dims, t.idx, rho, facs64, k, with_abs=True)
+        _, gabs = oracle.mttkrp(t.dims, t.idx, np.abs(t.vals) + mabs, facs64, k,
+                                with_abs=True)
+        refs.append((-2.0 * g, 2.0 * gabs))
+    return refs
+
+
+@pytest.mark.parametrize("case", LOSS_CASES)
+def test_loss_and_gradient_match_oracle(case):
+    say("loss case", case)
+    t, p, facs = _loss_case(case)
+    f64 = [f.astype(np.float64) for f in t.factors]
+    L_ref, G_ref = oracle.cp_loss_grad(t.dims, t.idx, t.vals, f64)
+    p.remap(1 % len(t.dims))                 # start away from L_0
+    loss, grads = p.cp_loss_grad(facs)
+    torch.cuda.synchronize()
+    assert p.cur_mode == 1 % len(t.dims)     # N passes end where they began
+    assert abs(loss.item() - L_ref) <= FP32_TOL * abs(L_ref)
+    refs = _grad_ref(t, f64)
+    for k in range(len(t.dims)):
+        g = grads[k].cpu().numpy()
+        # second route: the oracle's own gradient routine
+        assert np.linalg.norm(g - G_ref[k]) <= FP32_TOL * np.linalg.norm(G_ref[k])
+        check_close(g, refs[k][0], refs[k][1], FP32_TOL, f"grad {k}")
+    # bit-identical when repeated
+    loss2, grads2 = p.cp_loss_grad(facs)
+    assert loss2.item() == loss.item()
+    for a, b in zip(grads, grads2):
+        assert torch.equal(a, b)
+
+
+def test_gpu_forward_central_difference_matches_gpu_gradient():
+    """The loss is exactly quadratic in any single factor entry, so a large
+    step (h = 0.25) swamps FP32 rounding without truncation error."""
+    t, p, facs = _loss_case(((50, 40, 30), 3000, 16, 61, 64))
+    _, grads = p.cp_loss_grad(facs, loss=False)
+    rng = np.random.default_rng(3)
+    h = 0.25
+    for _ in range(12):
+        k = int(rng.integers(0, 3))
+        i = int(rng.choice(t.idx[k]))
+        r = int(rng.integers(0, 16))
+        fp = [f.clone() for f in facs]
+        fm = [f.clone() for f in facs]
+        fp[k][i, r] += h
+        fm[k][i, r] -= h
+        lp, _ = p.cp_loss_grad(fp, grads=False)
+        lm, _ = p.cp_loss_grad(fm, grads=False)
+        fd = (lp.item() - lm.item()) / (2 * h)
+        g = grads[k][i, r].item()
+        assert abs(fd - g) <= 1e-3 * max(1.0, abs(g)), (k, i, r, fd, g)
+
+
+def test_autograd_function_scales_by_upstream_gradient():
+    t, p, facs = _loss_case(((40, 30, 20), 2000, 16, 71, 64))
+    fr = [f.clone().requires_grad_(True) for f in facs]
+    loss = cp_loss(p, fr)
+    assert loss.dtype == torch.float64 and loss.requires_grad
+    (3.0 * loss).backward()
+    L_ref, G_ref = oracle.cp_loss_grad(t.dims, t.idx, t.vals, t.factors)
+    assert abs(loss.item() - L_ref) <= FP32_TOL * L_ref
+    for k in range(3):
+        g = fr[k].grad.cpu().numpy()
+        assert np.linalg.norm(g - 3.0 * G_ref[k]) <= FP32_TOL * 3.0 * np.linalg.norm(G_ref[k])
+    # only the factors that ask for gradients get them
+    fr2 = [facs[0].clone().requires_grad_(True), facs[1], facs[2]]
+    cp_loss(p, fr2).backward()
+    assert fr2[0].grad is not None
+
+
+def test_loss_at_planted_truth_matches_noise_level():
+    rng = np.random.default_rng(9)
+    dims, R, nnz = (400, 300, 200), 8, 60000
+    true = [rng.random((d, R)).astype(np.float32) for d in dims]
+    t = syn.random_tensor(dims, nnz, R, 81)
+    m = np.zeros(nnz)
+    for r in range(R):
+        m += true[0][t.idx[0], r].astype(np.float64) * true[1][t.idx[1], r] * true[2][t.idx[2], r]
+    sigma = 0.01 * np.sqrt(np.mean(m * m))
+    x = (m + sigma * rng.standard_normal(nnz)).astype(np.float32)
+    d = dev()
+    p = Plan(torch.from_numpy(t.idx).to(d), torch.from_numpy(x).to(d), dims, R, g=256)
+    loss, _ = p.cp_loss_grad([torch.from_numpy(a).to(d) for a in true], grads=False)
+    expect = nnz * sigma ** 2
+    # FP32 model values carry ~1e-7 relative error, far below sigma = 1e-2 RMS
+    assert abs(loss.item() - expect) < 5 * np.sqrt(2.0 / nnz) * expect + 1e-3 * expect
+
+
+ALS_CASES = [((60, 50, 40), 5000, 8, 91, 64), ((30, 4, 25, 20), 4000, 16, 92, 100),
+             ((80, 70, 60, 10, 5), 8000, 16, 93, 128), ((120, 100), 3000, 5, 94, 64)]
+
+
+@pytest.mark.parametrize("case", ALS_CASES)
+def test_cp_als_sweep_fp32(case):
+    dims, nnz, R, seed, g = case
+    say("als fp32 case", case)
+    t = syn.random_tensor(dims, nnz, R, seed)
+    idx, vals, facs = to_dev(t)
+    p = Plan(idx, vals, dims, R, g=g)
+    lam, fit = p.cp_als_sweep(facs)
+    of, olam, ofit, ridge, _ = oracle.cp_als_sweep(dims, t.idx, t.vals, t.factors)
+    assert ridge == 0 and p.info(_abi.INFO_RIDGE) == 0
+    assert p.cur_mode == 0
+    assert np.allclose(lam.cpu().numpy(), olam, rtol=1e-5, atol=0)
+    for n in range(len(dims)):
+        a = facs[n].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(a - of[n]) <= 1e-5 * np.linalg.norm(of[n]), n
+    assert abs(fit.item() - ofit) <= 1e-6, (fit.item(), ofit)
+
+
+@pytest.mark.parametrize("case", ALS_CASES[:3])
+def test_cp_als_sweep_bf16(case):
+    dims, nnz, R, seed, g = case
+    say("als bf16 case", case)
+    t = syn.random_tensor(dims, nnz, R, seed)
+    idx, vals, facs = to_dev(t, torch.bfloat16)
+    p = Plan(idx, vals, dims, R, g=g)
+    lam, fit = p.cp_als_sweep(facs)
+    of, olam, ofit, _, _ = oracle.cp_als_sweep(dims, t.idx, t.vals,
+                                               [bf16_round(f) for f in t.factors])
+    assert np.allclose(lam.cpu().numpy(), olam, rtol=BF16_TOL, atol=0)
+    for n in range(len(dims)):
+        a = facs[n].float().cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(a - of[n]) <= BF16_TOL * np.linalg.norm(of[n]), n
+        # stored values are BF16 round-to-nearest-even of an FP64 quantity:
+        # within half a BF16 ulp (2^-8 relative) of the oracle's factor
+        assert np.all(np.abs(a - of[n]) <= 2.0 ** -8 * np.abs(of[n]) + 1e-2 * np.abs(of[n]).max())
+    assert abs(fit.item() - ofit) <= BF16_TOL
+
+
+def test_cp_als_gpu_converges_on_planted_tensor():
+    rng = np.random.default_rng(5)
+    dims, R = (12, 10, 8), 3
+    true = [rng.standard_normal((d, R)) for d in dims]
+    X = np.einsum("ir,jr,kr->ijk", *true)
+    idx = np.array(np.unravel_index(np.arange(X.size), dims)).astype(np.int32)
+    vals = X.reshape(-1).astype(np.float32)
+    d = dev()
+    p = Plan(torch.from_numpy(idx).to(d), torch.from_numpy(vals).to(d), dims, R, g=64)
+    facs = [torch.from_numpy(rng.random((n, R)).astype(np.float32)).to(d) for n in dims]
+    fit = None
+    for _ in range(200):
+        lam, fit = p.cp_als_sweep(facs)
+    assert fit.item() > 1 - 1e-4, fit.item()
