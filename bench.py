@@ -4,7 +4,8 @@
 Workload (default): 3-mode COO tensor 50000 x 40000 x 30000, 20M distinct
 nonzeros with Zipf(1.2) coordinates over shuffled indices, lognormal(0,1)
 values, rank 32, N(0,1) FP32 factors; one step = MTTKRP along all three
-modes with the dynamic remap fused (the tensor ends where it started).
+modes, each followed by the dynamic remap into the next mode's layout (the
+tensor ends where it started).
 
 Reports one JSON line: whole-sweep algorithmic bytes / sweep time (GB/s),
 sweep ms, the per-mode kernel's roofline fraction against 8 TB/s HBM, the
@@ -33,11 +34,60 @@ def log(*a):
 
 
 def b_alg_mode(dims, nnz, R, n, sf):
-    """Algorithmic bytes of one mode: record read + remap write + gathered
-    input-factor rows + output write."""
+    """Algorithmic bytes of one mode in the paper's traffic model: record read
+    + remap write + gathered input-factor rows + output write."""
     N = len(dims)
     E = 4 * N + 4
     return nnz * E * 2 + nnz * (N - 1) * R * sf + dims[n] * R * 4
+
+
+def b_alg_mttkrp_kernel(dims, nnz, R, n, sf):
+    """Algorithmic bytes of one launch of the per-mode MTTKRP kernel (remap
+    done by its own kernel): record read + gathers + output write."""
+    N = len(dims)
+    return nnz * (4 * N + 4) + nnz * (N - 1) * R * sf + dims[n] * R * 4
+
+
+def b_alg_remap_kernel(dims, nnz):
+    """Record read + remap-target read + record write."""
+    E = 4 * len(dims) + 4
+    return nnz * (2 * E + 4)
+
+
+def b_min_mttkrp_kernel(dims, nnz, R, n, sf):
+    """Compulsory bytes: every record once, every input factor once, output."""
+    N = len(dims)
+    return nnz * (4 * N + 4) + sum(dims[w] * R * sf for w in range(N) if w != n) \
+        + dims[n] * R * 4
+
+
+def source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "paper_2309_09131_amd", "csrc")
+    for f in ("common.hpp", "mttkrp_kernels.hpp", "inst.hpp", "launch.hpp"):
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(path, key):
+    """Calibrated HBM bytes per launch from a committed rocprofv3 summary, or
+    None if missing or taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != source_sha():
+        return None
+    try:
+        return int(float(vals[key]))
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -50,6 +100,8 @@ def main():
     ap.add_argument("--natural-order", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the fused-remap ablation sweep")
     ap.add_argument("--copy-calib-mb", type=int, default=256,
                     help="size of a plain device copy run for counter calibration")
     args = ap.parse_args()
@@ -98,7 +150,8 @@ def main():
             plan.mttkrp_all_modes(factors, outs)
         torch.cuda.synchronize()
         plan.profile(True)
-        plan.profile_read()                      # reset
+        plan.profile_read(_abi.PROF_MTTKRP)      # reset
+        plan.profile_read(_abi.PROF_REMAP)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -108,20 +161,33 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         sweep_ms = e0.elapsed_time(e1) / steps
-        per_mode = [plan.profile_read(n) for n in range(N)]
+        per_mode = [plan.profile_read(_abi.PROF_MTTKRP, n) for n in range(N)]
+        per_remap = [plan.profile_read(_abi.PROF_REMAP, n) for n in range(N)]
         plan.profile(False)
-        return sweep_ms, per_mode
+        return sweep_ms, per_mode, per_remap
 
-    sweep_ms, per_mode = timed(f32, args.steps, args.warmup)
-    log(f"fp32 sweep {sweep_ms:.3f} ms; per-mode kernel ms "
-        f"{[round(m / max(c, 1), 4) for m, c in per_mode]}")
-    balg = [b_alg_mode(dims, nnz, R, n, 4) for n in range(N)]
-    sweep_bytes = sum(balg)
+    sweep_ms, per_mode, per_remap = timed(f32, args.steps, args.warmup)
+    log(f"fp32 sweep {sweep_ms:.3f} ms; per-mode MTTKRP kernel ms "
+        f"{[round(m / max(c, 1), 4) for m, c in per_mode]}; remap kernel ms "
+        f"{[round(m / max(c, 1), 4) for m, c in per_remap]}")
+    sweep_bytes = sum(b_alg_mode(dims, nnz, R, n, 4) for n in range(N))
     value = sweep_bytes / (sweep_ms * 1e-3) / 1e9
-    k_ms = sum(m for m, _ in per_mode)
-    k_launch = sum(c for _, c in per_mode)
-    k_bytes = sum(balg[n] * per_mode[n][1] for n in range(N))
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9
+
+    def kstats(times, bytes_of):
+        ms = sum(m for m, _ in times)
+        launches = sum(c for _, c in times)
+        nbytes = sum(bytes_of(n) * times[n][1] for n in range(N))
+        return ms / max(launches, 1), nbytes / max(launches, 1), \
+            nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+
+    mk_ms, mk_bytes, mk_gbs = kstats(per_mode, lambda n: b_alg_mttkrp_kernel(dims, nnz, R, n, 4))
+    rm_ms, rm_bytes, rm_gbs = kstats(per_remap, lambda n: b_alg_remap_kernel(dims, nnz))
+    mk_min = sum(b_min_mttkrp_kernel(dims, nnz, R, n, 4) for n in range(N)) / N
+    prof_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+    ctr = os.path.join(prof_dir, f"mttkrp_kernel_{w.name}_counters.txt")
+    fetch = counter_traffic(ctr, "fetch_bytes_per_launch")
+    write = counter_traffic(ctr, "write_bytes_per_launch")
+    traffic = (fetch + write) if (fetch is not None and write is not None) else None
 
     # errors on sampled rows against the FP64 oracle (FP32, then BF16)
     import oracle  # test infrastructure: error report and CPU baseline only
@@ -149,7 +215,7 @@ def main():
     err32 = errors(outs)
     result_bf16 = None
     if not args.no_bf16:
-        bms, bmode = timed(bf, args.steps, args.warmup)
+        bms, bmode, bremap = timed(bf, args.steps, args.warmup)
         plan.mttkrp_all_modes(bf, outs)
         torch.cuda.synchronize()
         errb = errors(outs)
@@ -158,6 +224,29 @@ def main():
                        "alg_GBs": round(bbytes / (bms * 1e-3) / 1e9, 1),
                        "error_vs_fp64_oracle": errb, "tolerance": 2e-2}
         log(f"bf16 sweep {bms:.3f} ms (x{sweep_ms / bms:.2f})")
+
+    def fused_sweep():
+        fplan = Plan(torch.from_numpy(T.idx).to(dev), torch.from_numpy(T.vals).to(dev), dims,
+                     R, g=args.g, flags=flags | _abi.FUSED_REMAP)
+        for _ in range(args.warmup):
+            fplan.mttkrp_all_modes(f32, outs)
+        torch.cuda.synchronize()
+        fe0 = torch.cuda.Event(enable_timing=True)
+        fe1 = torch.cuda.Event(enable_timing=True)
+        fe0.record()
+        for _ in range(args.steps):
+            fplan.mttkrp_all_modes(f32, outs)
+        fe1.record()
+        torch.cuda.synchronize()
+        fused_ms = fe0.elapsed_time(fe1) / args.steps
+        del fplan
+        return fused_ms
+
+    # ablation: remap inside the MTTKRP kernel (the paper's same-agent form)
+    fused_ms = None
+    if not args.no_ablation:
+        fused_ms = fused_sweep()
+    log(f"fused-remap fp32 sweep {fused_ms} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -178,19 +267,30 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "dims": list(dims), "nnz": nnz, "rank": R,
-                   "step": "MTTKRP along all modes with fused remap",
+                   "step": "MTTKRP along every mode, each followed by the dynamic "
+                           "remap of the tensor into the next mode's layout",
                    "shard_g": plan.info(_abi.INFO_G), "plan_ms": round(plan_ms, 1)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(mk_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "mk::mttkrp_kernel (per-mode MTTKRP + fused remap)",
-                     "kernel_ms_per_launch": round(k_ms / max(k_launch, 1), 4),
-                     "alg_bytes_per_launch": int(k_bytes / max(k_launch, 1))},
+                     "frac": round(mk_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "mk::mttkrp_kernel (per-mode MTTKRP)",
+                     "kernel_ms_per_launch": round(mk_ms, 4),
+                     "alg_bytes_per_launch": int(mk_bytes),
+                     "compulsory_bytes_per_launch": int(mk_min),
+                     "compulsory_frac": round(mk_min / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "note": "algorithmic bytes count every gathered factor row "
+                             "(paper's traffic model); most gathers hit L2/MALL"},
+        "remap_kernel": {"ms_per_launch": round(rm_ms, 4),
+                         "alg_bytes_per_launch": int(rm_bytes),
+                         "achieved_GBs": round(rm_gbs, 1),
+                         "frac": round(rm_gbs / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
         "sweep_ms": round(sweep_ms, 4),
         "per_mode_kernel_ms": [round(m / max(c, 1), 4) for m, c in per_mode],
+        "per_mode_remap_ms": [round(m / max(c, 1), 4) for m, c in per_remap],
         "fp32_error_vs_fp64_oracle": err32,
         "bf16": result_bf16,
+        "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
     }
     print(json.dumps(rec), flush=True)
 

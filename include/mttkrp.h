@@ -65,6 +65,10 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
 #define MTTKRP_NO_IMPLICIT_REMAP 1u  /* mttkrp_mode on another layout fails  */
 #define MTTKRP_NATURAL_ORDER 2u      /* dispatch shards in tensor order
                                         instead of longest-first order     */
+#define MTTKRP_FUSED_REMAP 4u        /* write L_{n+1} from inside the MTTKRP
+                                        kernel (the paper's same-agent remap)
+                                        instead of a remap kernel right after
+                                        it (default: measured faster here)  */
 
 /* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
 typedef struct {
@@ -108,8 +112,10 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz,
  * be NULL here).  d_out: I_mode x R FP32, fully overwritten (rows without
  * nonzeros become +0.0).  If the tensor is not in L_mode it is first
  * remapped forward (ESTATE instead under MTTKRP_NO_IMPLICIT_REMAP).
- * fuse_remap != 0 also writes L_{mode+1} in the same pass (Sec. III-B;
- * Sec. V-B: remap done by the computing agent) and leaves the plan there.
+ * fuse_remap != 0 also remaps the tensor to L_{mode+1} (Sec. III-B) and
+ * leaves the plan there: by a remap kernel enqueued right after the MTTKRP,
+ * or inside the MTTKRP pass itself (Sec. V-B, same agent) when the plan was
+ * built with MTTKRP_FUSED_REMAP.
  */
 mttkrp_status mttkrp_mode(mttkrp_plan_t p, int mode, const void *const *d_factors,
                           mttkrp_dtype fdt, float *d_out, int fuse_remap,
@@ -193,12 +199,15 @@ enum {
 mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *value);
 
 /* Kernel timing with HIP events on the launch stream: when enabled, every
- * per-mode MTTKRP kernel launch is bracketed by events.  mttkrp_profile_read
- * synchronises, returns the summed milliseconds and launch count of that
- * kernel for `mode` (-1: all modes) since the last reset, and resets the
- * events it read. */
+ * launch of the per-mode MTTKRP kernel and of the remap kernel is bracketed
+ * by events.  mttkrp_profile_read synchronises and returns the summed
+ * milliseconds and launch count of `kernel` (MTTKRP_PROF_MTTKRP or
+ * MTTKRP_PROF_REMAP) for `mode` (-1: all modes; for the remap kernel, the
+ * mode it remaps from) since the last read, and resets those events. */
+#define MTTKRP_PROF_MTTKRP 0
+#define MTTKRP_PROF_REMAP 1
 mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable);
-mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms,
+mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int kernel, int mode, double *ms,
                                   int64_t *launches);
 
 /* Frees the host object (never the caller's workspace). */

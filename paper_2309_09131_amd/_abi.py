@@ -19,6 +19,8 @@ OK, EINVAL, ERANGE, ENOMEM, ESTATE, EHIP = range(6)
 F32, BF16 = 0, 1
 NO_IMPLICIT_REMAP = 1
 NATURAL_ORDER = 2
+FUSED_REMAP = 4
+PROF_MTTKRP, PROF_REMAP = 0, 1
 Q_LAYOUT, Q_PERM, Q_ROW_PTR, Q_SHARDS, Q_LPT = range(5)
 INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2
 INFO_NSPLIT, INFO_G, INFO_M, INFO_RIDGE = 4, 5, 6, 7
@@ -66,7 +68,7 @@ def load():
         "mttkrp_plan_query": [_vp, _int, _int, _vp, ctypes.c_size_t, _vp],
         "mttkrp_plan_info": [_vp, _int, _int, ctypes.POINTER(_i64)],
         "mttkrp_profile": [_vp, _int],
-        "mttkrp_profile_read": [_vp, _int, ctypes.POINTER(ctypes.c_double),
+        "mttkrp_profile_read": [_vp, _int, _int, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(_i64)],
         "mttkrp_plan_destroy": [_vp],
         "mttkrp_status_str": [_int],
@@ -173,12 +175,12 @@ def mttkrp_profile(plan, enable):
     _check(lib.mttkrp_profile(plan, 1 if enable else 0), plan)
 
 
-def mttkrp_profile_read(plan, mode=-1):
+def mttkrp_profile_read(plan, kernel=0, mode=-1):
     lib = load()
     ms = ctypes.c_double(0.0)
     cnt = ctypes.c_int64(0)
-    _check(lib.mttkrp_profile_read(plan, mode, ctypes.byref(ms), ctypes.byref(cnt)),
-           plan)
+    _check(lib.mttkrp_profile_read(plan, kernel, mode, ctypes.byref(ms),
+                                   ctypes.byref(cnt)), plan)
     return ms.value, cnt.value
 
 

@@ -140,8 +140,9 @@ class Plan:
     def profile(self, enable=True):
         _abi.mttkrp_profile(self.handle, enable)
 
-    def profile_read(self, mode=-1):
-        return _abi.mttkrp_profile_read(self.handle, mode)
+    def profile_read(self, kernel=_abi.PROF_MTTKRP, mode=-1):
+        """(milliseconds, launches) of `kernel` since the last read."""
+        return _abi.mttkrp_profile_read(self.handle, kernel, mode)
 
 
 class CpLoss(torch.autograd.Function):

@@ -26,6 +26,36 @@ __device__ __forceinline__ void store_rec(uint32_t *__restrict__ buf, int64_t i,
     *reinterpret_cast<Rec<N> *>(buf + i * (N + 1)) = r;
 }
 
+// Streaming variants (non-temporal hint, per dword) for the record stream.
+template <int N>
+__device__ __forceinline__ Rec<N> load_rec_nt(const uint32_t *__restrict__ buf, int64_t i)
+{
+    Rec<N> r;
+    const uint32_t *p = buf + i * (N + 1);
+#pragma unroll
+    for (int k = 0; k < N + 1; ++k) r.w[k] = __builtin_nontemporal_load(p + k);
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ void store_rec_nt(uint32_t *__restrict__ buf, int64_t i, const Rec<N> &r)
+{
+    uint32_t *p = buf + i * (N + 1);
+#pragma unroll
+    for (int k = 0; k < N + 1; ++k) __builtin_nontemporal_store(r.w[k], p + k);
+}
+
+// Coordinate `n` (runtime) of a record without dynamic register indexing,
+// which would push the record to scratch memory.
+template <int N>
+__device__ __forceinline__ int rec_coord(const Rec<N> &r, int n)
+{
+    int v = (int)r.w[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) v = (n == k) ? (int)r.w[k] : v;
+    return v;
+}
+
 // bfloat16 storage <-> float.  Widening is exact (the 16 high bits).
 __device__ __forceinline__ float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }

@@ -29,11 +29,18 @@ namespace {
 template <typename FT, int LANES, int V, bool STRIDED>
 hipError_t launch_one(const Args &a, int kind, unsigned grid, hipStream_t s)
 {
-    if (kind == KIND_MTTKRP)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, false>), dim3(grid),
+    // separate instantiations with and without the in-kernel remap
+    if (kind == KIND_MTTKRP && a.rout)
+        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, false, true>), dim3(grid),
+                           dim3(256), 0, s, a);
+    else if (kind == KIND_MTTKRP)
+        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, false, false>), dim3(grid),
+                           dim3(256), 0, s, a);
+    else if (kind == KIND_RESID && a.rout)
+        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, true, true>), dim3(grid),
                            dim3(256), 0, s, a);
     else if (kind == KIND_RESID)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, true>), dim3(grid),
+        hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, true, false>), dim3(grid),
                            dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((loss_kernel<NM, FT, LANES, V, STRIDED>), dim3(grid), dim3(256), 0,
@@ -51,7 +58,9 @@ hipError_t launch_contig(const Args &a, int lanes, int kind, unsigned grid, hipS
     case 8: return launch_one<FT, 8, V, false>(a, kind, grid, s);
     case 16: return launch_one<FT, 16, V, false>(a, kind, grid, s);
     case 32: return launch_one<FT, 32, V, false>(a, kind, grid, s);
-    case 64: return launch_one<FT, 64, V, false>(a, kind, grid, s);
+    case 64:
+        if constexpr (V == 4 && sizeof(FT) == 4) return launch_one<FT, 64, V, false>(a, kind, grid, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -76,10 +85,12 @@ hipError_t launch_mttkrp<NM>(const Args &a, int bf16, LaneCfg c, int kind, unsig
     if (c.strided)
         return bf16 ? launch_strided<uint16_t>(a, c.j, kind, grid, s)
                     : launch_strided<float>(a, c.j, kind, grid, s);
+    // c.j selects the per-lane width for contiguous lanes: 1 = 16 bytes, 2 = 32
     if (bf16) {
-        if (c.lanes > 32) return hipErrorInvalidValue;
+        if (c.j == 2) return launch_contig<uint16_t, 16>(a, c.lanes, kind, grid, s);
         return launch_contig<uint16_t, 8>(a, c.lanes, kind, grid, s);
     }
+    if (c.j == 2) return launch_contig<float, 8>(a, c.lanes, kind, grid, s);
     return launch_contig<float, 4>(a, c.lanes, kind, grid, s);
 }
 

@@ -25,8 +25,9 @@ struct Args {
     double *partial;          // loss forward: one double per shard
 };
 
-// Lane configuration: contiguous (lanes = nextpow2(R / V), V = 16 bytes of
-// factor row per lane) or strided (64 lanes, J = ceil(R / 64) ranks each).
+// Lane configuration: contiguous (lanes = nextpow2(R / V); j = 2: V = 32
+// bytes of factor row per lane, j = 1: 16 bytes) or strided (64 lanes,
+// j = ceil(R / 64) ranks each).
 struct LaneCfg {
     int lanes;
     int j;

@@ -49,6 +49,34 @@ struct Fetch<float, 4, false> {
 };
 
 template <>
+struct Fetch<float, 8, false> {
+    static __device__ __forceinline__ void get(const void *A, int64_t row, int R, int sub,
+                                               float (&x)[8])
+    {
+        const float4 *q = reinterpret_cast<const float4 *>(
+            reinterpret_cast<const float *>(A) + row * R + sub * 8);
+        const float4 v0 = q[0], v1 = q[1];
+        x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+        x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+    }
+};
+
+template <>
+struct Fetch<uint16_t, 16, false> {
+    static __device__ __forceinline__ void get(const void *A, int64_t row, int R, int sub,
+                                               float (&x)[16])
+    {
+        const uint4 *q = reinterpret_cast<const uint4 *>(
+            reinterpret_cast<const uint16_t *>(A) + row * R + sub * 16);
+        const uint4 u0 = q[0], u1 = q[1];
+        x[0] = bf16lo(u0.x); x[1] = bf16hi(u0.x); x[2] = bf16lo(u0.y); x[3] = bf16hi(u0.y);
+        x[4] = bf16lo(u0.z); x[5] = bf16hi(u0.z); x[6] = bf16lo(u0.w); x[7] = bf16hi(u0.w);
+        x[8] = bf16lo(u1.x); x[9] = bf16hi(u1.x); x[10] = bf16lo(u1.y); x[11] = bf16hi(u1.y);
+        x[12] = bf16lo(u1.z); x[13] = bf16hi(u1.z); x[14] = bf16lo(u1.w); x[15] = bf16hi(u1.w);
+    }
+};
+
+template <>
 struct Fetch<uint16_t, 8, false> {
     static __device__ __forceinline__ void get(const void *A, int64_t row, int R, int sub,
                                                float (&x)[8])
@@ -70,8 +98,9 @@ struct Fetch<float, V, true> {
         const float *p = reinterpret_cast<const float *>(A) + row * R;
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            int r = sub + 64 * j;
-            x[j] = (r < R) ? p[r] : 0.0f;
+            const int r = sub + 64 * j;
+            const float v = p[r < R ? r : R - 1];     // clamped: no branch
+            x[j] = (r < R) ? v : 0.0f;
         }
     }
 };
@@ -84,8 +113,9 @@ struct Fetch<uint16_t, V, true> {
         const uint16_t *p = reinterpret_cast<const uint16_t *>(A) + row * R;
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            int r = sub + 64 * j;
-            x[j] = (r < R) ? bf16_to_f32(p[r]) : 0.0f;
+            const int r = sub + 64 * j;
+            const float v = bf16_to_f32(p[r < R ? r : R - 1]);
+            x[j] = (r < R) ? v : 0.0f;
         }
     }
 };
@@ -114,18 +144,51 @@ __device__ __forceinline__ bool lane_active(int sub, int R)
     else return sub * V < R;
 }
 
-// Product of the factor rows of every mode except `skip` (skip = -1: all).
+// The N-1 input modes of output mode n, in increasing order (uniform).
+template <int N>
+struct Inputs {
+    const void *fac[N > 1 ? N - 1 : 1];
+    int mode[N > 1 ? N - 1 : 1];
+    __device__ __forceinline__ Inputs(const Args &a, int n)
+    {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) {
+            const int w = k + (k >= n ? 1 : 0);
+            mode[k] = w;
+            fac[k] = a.fac[w];
+        }
+    }
+};
+
+// Hadamard product of the input factor rows of one nonzero.  Every load is
+// unconditional (the caller passes an in-range record and lane), so the
+// compiler can keep all gathers of an unrolled group in flight at once.
 template <int N, typename FT, int V, bool STRIDED>
-__device__ __forceinline__ void row_product(const Args &a, const Rec<N> &rc, int skip, int sub,
-                                            float (&pr)[V])
+__device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<N> &rc, int R,
+                                            int sub, float (&pr)[V])
+{
+#pragma unroll
+    for (int j = 0; j < V; ++j) pr[j] = 1.0f;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        float x[V];
+        Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)rec_coord<N>(rc, in.mode[k]), R, sub, x);
+#pragma unroll
+        for (int j = 0; j < V; ++j) pr[j] *= x[j];
+    }
+}
+
+// Product over all N modes (loss forward).
+template <int N, typename FT, int V, bool STRIDED>
+__device__ __forceinline__ void row_product_all(const Args &a, const Rec<N> &rc, int R, int sub,
+                                                float (&pr)[V])
 {
 #pragma unroll
     for (int j = 0; j < V; ++j) pr[j] = 1.0f;
 #pragma unroll
     for (int w = 0; w < N; ++w) {
-        if (w == skip) continue;
         float x[V];
-        Fetch<FT, V, STRIDED>::get(a.fac[w], (int64_t)rc.w[w], a.R, sub, x);
+        Fetch<FT, V, STRIDED>::get(a.fac[w], (int64_t)rc.w[w], R, sub, x);
 #pragma unroll
         for (int j = 0; j < V; ++j) pr[j] *= x[j];
     }
@@ -141,16 +204,28 @@ __device__ __forceinline__ float slot_sum(float v)
 }
 
 // ---- per-mode MTTKRP (RESID = false) / loss-gradient pass (RESID = true) --
-template <int N, typename FT, int LANES, int V, bool STRIDED, bool RESID>
+// The wave's shard is cut into SW equal contiguous runs, one per slot.  A
+// slot walks its run in order, U nonzeros per iteration (all their loads
+// issued before the first use), accumulating the current row in registers:
+// a row that starts and ends inside the run is complete and written at
+// once.  The first row of each run (head) and the last (tail) are then
+// joined across slots with one segmented scan per shard.
+template <int N, typename FT, int LANES, int V, bool STRIDED, bool RESID, bool FUSE>
 __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
+#ifdef MK_U
+    constexpr int U = MK_U;
+#else
+    constexpr int U = 4;
+#endif
     const int lane = threadIdx.x & 63;
     const int sidx = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (sidx >= a.nshards) return;                         // whole wave
     const int shard = a.order ? a.order[sidx] : sidx;
     const int start = a.shards[3 * shard];
-    const int end = start + a.shards[3 * shard + 1];
+    const int len = a.shards[3 * shard + 1];
+    const int end = start + len;
     const int n = a.mode, R = a.R;
     const int slot = lane / LANES, sub = lane % LANES;
     const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
@@ -161,89 +236,143 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
     if constexpr (RESID) coef = -2.0f * (a.gscale ? (float)a.gscale[0] : 1.0f);
     float *const cbase = a.carry + (int64_t)shard * 2 * R;
 
-    // flush of a row that is complete inside this shard or is its first row
-    auto flush_mid = [&](int row, const float (&v)[V]) {
-        float *dst = (row == f && split_before) ? cbase : a.out + (int64_t)row * R;
-        store_row<V, STRIDED>(dst, R, sub, v);
-    };
+    float *const out = a.out;
+    // a complete row, or the shard's first row when it began earlier
+#define FLUSH_MID(row, v)                                                            \
+    store_row<V, STRIDED>(((row) == f && split_before) ? cbase : out + (int64_t)(row) * R, \
+                          R, sub, v)
 
-    float carry[V];
+    const int run = (len + SW - 1) / SW;
+    const int s0 = start + slot * run;
+    const int s1 = min(s0 + run, end);           // s0 >= s1: empty run (row l)
+    int cur_row = (s0 < s1) ? (int)a.rin[(int64_t)s0 * (N + 1) + n] : l;
+    const int head_row = cur_row;
+    bool in_head = true;
+    float acc[V], head[V];
 #pragma unroll
-    for (int j = 0; j < V; ++j) carry[j] = 0.0f;
-    int carry_row = -1;
+    for (int j = 0; j < V; ++j) { acc[j] = 0.0f; head[j] = 0.0f; }
 
-    for (int base = start; base < end; base += SW) {
-        const int e = base + slot;
-        const bool valid = e < end;
-        float p[V], pr[V];
-        int row = l;                       // invalid tail slots join row l
-        float val = 0.0f, m = 0.0f;
+    const Inputs<N> in(a, n);
+    const int fsub = ract ? sub : 0;             // in-range lane for loads
+    for (int k = 0; k < run; k += U) {           // uniform trip count
+        Rec<N> rc[U];
+        bool ok[U];
 #pragma unroll
-        for (int j = 0; j < V; ++j) { p[j] = 0.0f; pr[j] = 0.0f; }
-        if (valid) {
-            const Rec<N> rc = load_rec<N>(a.rin, e);
-            row = (int)rc.w[n];
-            if (a.rout && sub == 0) store_rec<N>(a.rout, a.perm[e], rc);
-            if (ract) {
-                val = __uint_as_float(rc.w[N]);
-                row_product<N, FT, V, STRIDED>(a, rc, n, sub, pr);
-                if constexpr (RESID) {
-                    float xn[V];
-                    Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)row, R, sub, xn);
+        for (int u = 0; u < U; ++u) {
+            const int e = s0 + k + u;
+            ok[u] = (k + u < run) && (e < end);
+#ifdef MK_NT_REC
+            rc[u] = load_rec_nt<N>(a.rin, ok[u] ? e : start);
+#else
+            rc[u] = load_rec<N>(a.rin, ok[u] ? e : start);   // clamped, no branch
+#endif
+        }
+        float pr[U][V];
+        float mm[U];
 #pragma unroll
-                    for (int j = 0; j < V; ++j) m += pr[j] * xn[j];
+        for (int u = 0; u < U; ++u) {
+            row_product<N, FT, V, STRIDED>(in, rc[u], R, fsub, pr[u]);
+            mm[u] = 0.0f;
+            if constexpr (RESID) {
+                float xn[V];
+                Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)rec_coord<N>(rc[u], n), R, fsub, xn);
+#pragma unroll
+                for (int j = 0; j < V; ++j) mm[u] += pr[u][j] * xn[j];
+                if (!(ok[u] && ract)) mm[u] = 0.0f;
+            }
+        }
+        if constexpr (FUSE) {
+            int dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) dst[u] = a.perm[ok[u] ? s0 + k + u : start];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#ifdef MK_NT_REMAP
+                if (ok[u] && sub == 0) store_rec_nt<N>(a.rout, dst[u], rc[u]);
+#else
+                if (ok[u] && sub == 0) store_rec<N>(a.rout, dst[u], rc[u]);
+#endif
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float c = 0.0f;
+            if constexpr (RESID) {
+                // model value m_e (lanes outside the rank range hold 0)
+                const float m = slot_sum<LANES>(mm[u]);
+                if (ok[u]) c = coef * (__uint_as_float(rc[u].w[N]) - m);
+            } else {
+                if (ok[u]) c = __uint_as_float(rc[u].w[N]);
+            }
+            if (ok[u]) {
+                const int row = (int)rec_coord<N>(rc[u], n);
+                if (row != cur_row) {
+                    if (in_head) {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) head[j] = acc[j];
+                        in_head = false;
+                    } else if (ract) {
+                        // interior row: starts and ends inside this run
+                        store_row<V, STRIDED>(out + (int64_t)cur_row * R, R, sub, acc);
+                    }
+#pragma unroll
+                    for (int j = 0; j < V; ++j) acc[j] = 0.0f;
+                    cur_row = row;
                 }
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[j] += c * pr[u][j];
             }
         }
-        if constexpr (RESID) {
-            // model value m_e: lanes outside the rank range hold 0
-            m = slot_sum<LANES>(m);
-            const float c = coef * (val - m);
-#pragma unroll
-            for (int j = 0; j < V; ++j) p[j] = c * pr[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) p[j] = val * pr[j];
-        }
-        // segmented inclusive scan over the SW slots (segments = equal rows)
-        const int prow = __shfl_up(row, LANES);
-        const bool head = (slot == 0) || (prow != row);
-        const uint64_t hm = __ballot(head && sub == 0);
-        const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-        const int sstart = (63 - __clzll(hm & upto)) / LANES;
-#pragma unroll
-        for (int d = 1; d < SW; d <<= 1) {
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const float t = __shfl_up(p[j], d * LANES);
-                if (slot - d >= sstart) p[j] += t;
-            }
-        }
-        const int nrow = __shfl_down(row, LANES);
-        const bool tail = (slot == SW - 1) || (nrow != row);
-        const int row0 = __shfl(row, 0);
-        if (row0 == carry_row) {
-            if (sstart == 0) {
-#pragma unroll
-                for (int j = 0; j < V; ++j) p[j] += carry[j];
-            }
-        } else if (carry_row >= 0) {
-            if (slot == 0 && ract) flush_mid(carry_row, carry);
-        }
-        if (tail && slot != SW - 1 && ract) flush_mid(row, p);
-#pragma unroll
-        for (int j = 0; j < V; ++j) carry[j] = __shfl(p[j], (SW - 1) * LANES + sub);
-        carry_row = __shfl(row, (SW - 1) * LANES);
     }
-    // the shard's last row: complete, or a partial (first or last slot)
-    if (slot == 0 && ract) {
-        const bool split_after = a.row_ptr[l + 1] > end;
-        float *dst;
-        if (l == f && split_before) dst = cbase;
-        else if (split_after) dst = cbase + (l == f ? 0 : R);
-        else dst = a.out + (int64_t)l * R;
-        store_row<V, STRIDED>(dst, R, sub, carry);
+    const bool single = in_head;                 // whole run is one row
+    const int tail_row = cur_row;
+    if (single) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) head[j] = acc[j];
     }
+    // join tails to the heads that continue them: segmented scan over slots
+    const int prev_tail = __shfl_up(tail_row, LANES);
+    const bool link = (slot > 0) && (prev_tail == head_row);
+    const bool hflag = !(single && link);
+    const uint64_t hm = __ballot(hflag && sub == 0);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int sstart = (63 - __clzll(hm & upto)) / LANES;
+    float c[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) c[j] = acc[j];
+#pragma unroll
+    for (int d = 1; d < SW; d <<= 1) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const float t = __shfl_up(c[j], d * LANES);
+            if (slot - d >= sstart) c[j] += t;
+        }
+    }
+    float cin[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const float t = __shfl_up(c[j], LANES);
+        cin[j] = link ? t : 0.0f;
+    }
+    const bool next_link = __shfl_down((int)link, LANES) != 0;
+    if (ract) {
+        if (!single) {
+            float h[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) h[j] = head[j] + cin[j];
+            FLUSH_MID(head_row, h);
+        }
+        if (slot < SW - 1 && !next_link) FLUSH_MID(tail_row, c);
+        if (slot == SW - 1) {
+            // the shard's last row: complete, or a boundary partial
+            const bool split_after = a.row_ptr[l + 1] > end;
+            float *dst;
+            if (l == f && split_before) dst = cbase;
+            else if (split_after) dst = cbase + (l == f ? 0 : R);
+            else dst = out + (int64_t)l * R;
+            store_row<V, STRIDED>(dst, R, sub, c);
+        }
+    }
+#undef FLUSH_MID
 }
 
 // ---- sampled CP loss forward: one double partial per shard ---------------
@@ -251,6 +380,7 @@ template <int N, typename FT, int LANES, int V, bool STRIDED>
 __global__ __launch_bounds__(256) void loss_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
+    constexpr int U = 4;
     const int lane = threadIdx.x & 63;
     const int sidx = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (sidx >= a.nshards) return;
@@ -260,23 +390,32 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
     const int slot = lane / LANES, sub = lane % LANES;
     const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
     double acc = 0.0;
-    for (int base = start; base < end; base += SW) {
-        const int e = base + slot;
-        float m = 0.0f, val = 0.0f;
-        if (e < end) {
-            const Rec<N> rc = load_rec<N>(a.rin, e);
-            val = __uint_as_float(rc.w[N]);
-            if (ract) {
-                float pr[V];
-                row_product<N, FT, V, STRIDED>(a, rc, -1, sub, pr);
+    for (int base = start; base < end; base += U * SW) {
+        Rec<N> rc[U];
+        float m[U];
 #pragma unroll
-                for (int j = 0; j < V; ++j) m += pr[j];
-            }
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * SW + slot;
+            rc[u] = load_rec<N>(a.rin, e < end ? e : start);   // clamped, no branch
         }
-        m = slot_sum<LANES>(m);
-        if (e < end && sub == 0) {
-            const float rho = val - m;
-            acc += (double)(rho * rho);    // FP32 term, FP64 accumulation
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * SW + slot;
+            float pr[V];
+            row_product_all<N, FT, V, STRIDED>(a, rc[u], R, ract ? sub : 0, pr);
+            m[u] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < V; ++j) m[u] += pr[j];
+            if (!(e < end && ract)) m[u] = 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = base + u * SW + slot;
+            const float mu = slot_sum<LANES>(m[u]);
+            if (e < end && sub == 0) {
+                const float rho = __uint_as_float(rc[u].w[N]) - mu;
+                acc += (double)(rho * rho);    // FP32 term, FP64 accumulation
+            }
         }
     }
     acc = wave_sum_d(acc);

@@ -41,6 +41,7 @@ struct Layout {
     size_t off_scratch, scratch_bytes, total;
     // runtime scratch (inside scratch)
     size_t rt_carry, rt_partial, rt_G, rt_L, rt_Linv, rt_W, rt_gpart, rt_colsq, rt_lambda_tmp;
+    size_t rt_seg[2], rt_segk[2];
     // plan scratch (inside scratch)
     size_t ps_k0, ps_k1, ps_v0, ps_v1, ps_o0, ps_o1, ps_hist, ps_hscan, ps_sums, ps_err;
 };
@@ -112,6 +113,11 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     L->rt_gpart = rtake((size_t)GRAM_TARGET_BLOCKS * 256 * 8 + (size_t)R * R * 8);
     L->rt_colsq = rtake((size_t)als::APPLY_BLOCKS * R * 8);
     L->rt_lambda_tmp = rtake((size_t)R * 8 + 64);
+    const int64_t seg_entries = maxS / 64 + 8;     // >= 2 * ceil(2 * maxS / 256)
+    L->rt_seg[0] = rtake((size_t)seg_entries * R * 4);
+    L->rt_seg[1] = rtake((size_t)seg_entries * R * 4);
+    L->rt_segk[0] = rtake((size_t)seg_entries * 4);
+    L->rt_segk[1] = rtake((size_t)seg_entries * 4);
     // plan scratch
     size_t p0 = 0;
     auto ptake = [&](size_t bytes) { size_t o = p0; p0 = align_up(p0 + bytes); return o; };
@@ -132,7 +138,7 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     return MTTKRP_OK;
 }
 
-struct ProfEvent { hipEvent_t a, b; int mode; };
+struct ProfEvent { hipEvent_t a, b; int mode; int kernel; };
 
 }  // namespace
 
@@ -142,7 +148,8 @@ struct mttkrp_plan_s {
     int cur = 0;            // layout the tensor is in
     int buf = 0;            // record buffer holding it
     int64_t nshards[MTTKRP_MAX_MODES] = {};
-    int64_t nsplit[MTTKRP_MAX_MODES] = {};
+    int64_t nsplit[MTTKRP_MAX_MODES] = {};   // rows split across shards
+    int64_t npart[MTTKRP_MAX_MODES] = {};    // their boundary partials (P0)
     int64_t nempty[MTTKRP_MAX_MODES] = {};
     std::string err;
     bool prof = false;
@@ -248,33 +255,118 @@ __global__ void fill_zero_kernel(float *__restrict__ p, int64_t n)
         p[i] = 0.0f;
 }
 
-// One block per row split across shards: adds the boundary partials of the
-// shards it spans in a fixed order (interleaved groups, then a tree) and
-// writes the row.  split[k] = {row, first shard, last shard, entry used in
-// the first shard}; later shards use entry 0.
-__global__ __launch_bounds__(256) void carry_fixup_kernel(const int32_t *__restrict__ split,
-                                                          const float *__restrict__ carry,
-                                                          float *__restrict__ out, int R, int RL)
+// Deterministic segmented reduction of the shard boundary partials of rows
+// split across shards (one level).  Entries are R-float vectors with sorted
+// row keys (level 0: read through `ids` from the per-shard partial slots).
+// Block b takes entries [b*SEG_B, (b+1)*SEG_B): slots of RL lanes walk runs
+// in order; rows wholly inside the block are written to `out`; the block's
+// first and last rows go to the next level as two entries (or to `out`
+// when this is the last level).  Fixed partition and order: bit-exact reruns.
+constexpr int SEG_B = 256;
+
+__global__ __launch_bounds__(256) void seg_reduce_kernel(const float *__restrict__ src,
+                                                         const int32_t *__restrict__ ids,
+                                                         const int32_t *__restrict__ keys,
+                                                         int64_t P, int R, int RL,
+                                                         float *__restrict__ out,
+                                                         float *__restrict__ next,
+                                                         int32_t *__restrict__ next_keys,
+                                                         int last_level)
 {
-    __shared__ float sh[256];
-    const int k = blockIdx.x;
-    const int row = split[4 * k], s0 = split[4 * k + 1], s1 = split[4 * k + 2],
-              e0 = split[4 * k + 3];
-    const int r = threadIdx.x % RL, q = threadIdx.x / RL, G = 256 / RL;
-    const int cnt = s1 - s0 + 1;
-    float acc = 0.0f;
-    if (r < R)
-        for (int i = q; i < cnt; i += G) {
-            const int64_t ent = (i == 0) ? (int64_t)s0 * 2 + e0 : (int64_t)(s0 + i) * 2;
-            acc += carry[ent * R + r];
+    __shared__ int32_t s_head[256], s_tail[256], s_single[256];
+    __shared__ float s_hsum[2 * 256];          // [SL][R] heads, then tails (SL*R <= 256)
+    const int SL = 256 / RL;
+    const int r = threadIdx.x % RL, slot = threadIdx.x / RL;
+    const int64_t b0 = (int64_t)blockIdx.x * SEG_B;
+    const int64_t b1 = (b0 + SEG_B < P) ? b0 + SEG_B : P;
+    const int run = (SEG_B + SL - 1) / SL;
+    const int64_t s0 = b0 + (int64_t)slot * run;
+    const int64_t s1 = (s0 + run < b1) ? s0 + run : b1;
+    const int first_row = keys[b0];
+    float *hs = s_hsum;
+    float *ts = s_hsum + SL * R;
+    // per-slot sequential pass
+    int cur = -1, head = -1;
+    bool single = true;
+    float acc = 0.0f, hsum = 0.0f;
+    for (int64_t e = s0; e < s1; ++e) {
+        const int row = keys[e];
+        const int64_t ent = ids ? (int64_t)ids[e] : e;
+        const float v = (r < R) ? src[ent * R + r] : 0.0f;
+        if (cur < 0) {
+            cur = head = row;
+        } else if (row != cur) {
+            if (single) {
+                hsum = acc;
+                single = false;
+            } else if (r < R) {
+                out[(int64_t)cur * R + r] = acc;      // interior row
+            }
+            acc = 0.0f;
+            cur = row;
         }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = G / 2; h >= 1; h >>= 1) {
-        if (q < h) sh[threadIdx.x] += sh[threadIdx.x + h * RL];
-        __syncthreads();
+        acc += v;
     }
-    if (q == 0 && r < R) out[(int64_t)row * R + r] = sh[threadIdx.x];
+    if (single) hsum = acc;
+    if (r == 0) {
+        s_head[slot] = head;
+        s_tail[slot] = cur;
+        s_single[slot] = single ? 1 : 0;
+    }
+    if (r < R) {
+        hs[slot * R + r] = hsum;
+        ts[slot * R + r] = acc;
+    }
+    __syncthreads();
+    // one group of RL lanes joins the slots in order
+    if (slot != 0) return;
+    int row = -1;
+    float sum = 0.0f;
+    auto flush = [&](int rw, float v) {
+        if (rw == first_row && !last_level) {
+            if (r < R) next[(2 * (int64_t)blockIdx.x) * R + r] = v;
+        } else if (r < R) {
+            out[(int64_t)rw * R + r] = v;
+        }
+    };
+    bool first_flushed = false;
+    for (int k = 0; k < SL; ++k) {
+        const int h = s_head[k];
+        if (h < 0) continue;                      // empty slot
+        const float hv = (r < R) ? hs[k * R + r] : 0.0f;
+        if (row == h) {
+            sum += hv;
+        } else {
+            if (row >= 0) {
+                flush(row, sum);
+                first_flushed |= (row == first_row);
+            }
+            row = h;
+            sum = hv;
+        }
+        if (!s_single[k]) {
+            flush(row, sum);
+            first_flushed |= (row == first_row);
+            row = s_tail[k];
+            sum = (r < R) ? ts[k * R + r] : 0.0f;
+        }
+    }
+    // the block's last row (may equal its first row)
+    if (last_level) {
+        if (r < R) out[(int64_t)row * R + r] = sum;
+    } else {
+        float *e0 = next + (2 * (int64_t)blockIdx.x) * R;
+        float *e1 = e0 + R;
+        if (row == first_row && !first_flushed) {
+            if (r < R) { e0[r] = sum; e1[r] = 0.0f; }
+        } else if (r < R) {
+            e1[r] = sum;
+        }
+        if (r == 0) {
+            next_keys[2 * blockIdx.x] = first_row;
+            next_keys[2 * blockIdx.x + 1] = row;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- helpers
@@ -291,11 +383,16 @@ static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 static mk::LaneCfg lane_cfg(int R, mttkrp_dtype fdt, const void *const *facs, int N,
                             const float *out)
 {
-    const int V = (fdt == MTTKRP_BF16) ? 8 : 4;
-    bool ok = (R % V == 0) && (out == nullptr || aligned16(out));
+    // 32 bytes of factor row per lane when R allows it (measured fastest on
+    // gfx950: fewer lanes repeat each record load), else 16 bytes, else the
+    // strided form for ranks that are not multiples of the vector width
+    const int V16 = (fdt == MTTKRP_BF16) ? 8 : 4;
+    bool ok = (R % V16 == 0) && (out == nullptr || aligned16(out));
     for (int w = 0; w < N && ok; ++w)
         if (facs[w] && !aligned16(facs[w])) ok = false;
-    if (ok && next_pow2(R / V) <= 64) return mk::LaneCfg{next_pow2(R / V), 1, false};
+    if (ok && R % (2 * V16) == 0 && next_pow2(R / (2 * V16)) <= 32)
+        return mk::LaneCfg{next_pow2(R / (2 * V16)), 2, false};
+    if (ok && next_pow2(R / V16) <= 64) return mk::LaneCfg{next_pow2(R / V16), 1, false};
     return mk::LaneCfg{64, (R + 63) / 64, true};
 }
 
@@ -341,7 +438,7 @@ static int key_bits(int64_t I)
 static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
                          std::vector<int32_t> &shards, std::vector<int32_t> &order,
                          std::vector<int32_t> &split, std::vector<int32_t> &lpt_bin,
-                         int64_t *nempty)
+                         int64_t *nempty, int64_t *nsplit_rows)
 {
     const int64_t I = L.dims[n], m = L.m[n], k = L.k[n], g = L.g;
     std::vector<int64_t> ss_first(k), ss_cnt(k);
@@ -380,30 +477,32 @@ static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
             for (int64_t q = 0; q < ss_cnt[ord[a]]; ++q)
                 order.push_back((int32_t)(ss_first[ord[a]] + q));
     }
-    // rows split across consecutive shards
+    // rows split across consecutive shards, flattened for the segmented
+    // reduction: for each such row, the partial slots (2*shard + entry) of the
+    // shards it spans, in shard order, keyed by the row
     auto row_of = [&](int64_t pos) {   // row r with rp[r] <= pos < rp[r+1]
         auto it = std::upper_bound(rp.begin(), rp.end(), (int32_t)pos);
         return (int64_t)(it - rp.begin()) - 1;
     };
-    split.clear();
-    bool open = false;
+    std::vector<int32_t> ids, keys;
+    int64_t rows_split = 0;
     for (int64_t s = 0; s < S; ++s) {
         const int64_t st = shards[3 * s], en = st + shards[3 * s + 1];
         const int64_t f = row_of(st), l = row_of(en - 1);
         const bool sb = rp[f] < st, sa = rp[l + 1] > en;
-        if (sb) {                       // continues an open split row
-            split[split.size() - 2] = (int32_t)s;
-            if (!(l == f && sa)) open = false;
+        if (sb) {                       // continues a split row: entry 0
+            ids.push_back((int32_t)(2 * s));
+            keys.push_back((int32_t)f);
         }
-        if (sa && !(l == f && sb)) {    // opens a new split row
-            split.push_back((int32_t)l);
-            split.push_back((int32_t)s);
-            split.push_back((int32_t)s);
-            split.push_back(l == f ? 0 : 1);
-            open = true;
+        if (sa && !(l == f && sb)) {    // opens a split row
+            ids.push_back((int32_t)(2 * s + (l == f ? 0 : 1)));
+            keys.push_back((int32_t)l);
+            ++rows_split;
         }
     }
-    (void)open;
+    split.assign(ids.begin(), ids.end());
+    split.insert(split.end(), keys.begin(), keys.end());
+    *nsplit_rows = rows_split;
     int64_t ne = 0;
     for (int64_t r = 0; r < I; ++r) ne += (rp[r] == rp[r + 1]);
     *nempty = ne;
@@ -433,10 +532,22 @@ static hipEvent_t take_event(mttkrp_plan_t p)
 }
 
 // Remap kernel run: L_cur -> L_cur+1.
+static hipEvent_t take_event(mttkrp_plan_t p);
+
 static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
 {
     const Layout &L = p->L;
+    ProfEvent ev{nullptr, nullptr, p->cur, 1};
+    if (p->prof) {
+        ev.a = take_event(p);
+        ev.b = take_event(p);
+        if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
+    }
     HIPCHK(p, launch_remap_any(L.N, p->rec(p->buf), p->rec(p->buf ^ 1), p->perm(p->cur), L.nnz, s));
+    if (p->prof) {
+        if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
+        p->events.push_back(ev);
+    }
     p->buf ^= 1;
     p->cur = (p->cur + 1) % L.N;
     return MTTKRP_OK;
@@ -460,8 +571,11 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     }
     mk::Args a;
     memset(&a, 0, sizeof(a));
+    // remap inside the MTTKRP kernel only when the plan asks for it; by
+    // default the remap runs as its own kernel right after (faster here)
+    const bool infuse = fuse && (L.flags & MTTKRP_FUSED_REMAP);
     a.rin = p->rec(p->buf);
-    a.rout = fuse ? p->rec(p->buf ^ 1) : nullptr;
+    a.rout = infuse ? p->rec(p->buf ^ 1) : nullptr;
     a.perm = p->perm(n);
     a.row_ptr = p->rp(n);
     a.shards = p->sh(n);
@@ -476,7 +590,7 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.partial = p->rt<double>(L.rt_partial);
     const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
     const unsigned grid = (unsigned)((p->nshards[n] + 3) / 4);
-    ProfEvent ev{nullptr, nullptr, n};
+    ProfEvent ev{nullptr, nullptr, n, 0};
     const bool prof = p->prof && kind == mk::KIND_MTTKRP;
     if (prof) {
         ev.a = take_event(p);
@@ -488,15 +602,32 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);
     }
-    if (kind != mk::KIND_LOSS && p->nsplit[n] > 0) {
+    if (kind != mk::KIND_LOSS && p->npart[n] > 0) {
         const int RL = std::min(256, next_pow2(L.R));
-        hipLaunchKernelGGL(carry_fixup_kernel, dim3((unsigned)p->nsplit[n]), dim3(256), 0, s,
-                           p->split(n), a.carry, out, L.R, RL);
-        HIPCHK(p, hipGetLastError());
+        const float *src = a.carry;
+        const int32_t *ids = p->split(n);
+        const int32_t *keys = p->split(n) + p->npart[n];
+        int64_t P = p->npart[n];
+        for (int lvl = 0;; ++lvl) {
+            const int64_t nb = (P + SEG_B - 1) / SEG_B;
+            const int last = nb == 1;
+            float *nx = p->rt<float>(L.rt_seg[lvl & 1]);
+            int32_t *nk = p->rt<int32_t>(L.rt_segk[lvl & 1]);
+            hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, src, ids,
+                               keys, P, L.R, RL, out, nx, nk, last);
+            HIPCHK(p, hipGetLastError());
+            if (last) break;
+            src = nx;
+            keys = nk;
+            ids = nullptr;
+            P = 2 * nb;
+        }
     }
-    if (fuse) {
+    if (infuse) {
         p->buf ^= 1;
         p->cur = (n + 1) % L.N;
+    } else if (fuse) {
+        return remap_step(p, s);
     }
     return MTTKRP_OK;
 }
@@ -643,9 +774,9 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return bail(fail(p, MTTKRP_EHIP, "row pointer copy"));
-        build_tables(L, n, rp, shards, order, split, bins, &p->nempty[n]);
+        build_tables(L, n, rp, shards, order, split, bins, &p->nempty[n], &p->nsplit[n]);
         p->nshards[n] = (int64_t)shards.size() / 3;
-        p->nsplit[n] = (int64_t)split.size() / 4;
+        p->npart[n] = (int64_t)split.size() / 2;
         if (p->nshards[n] > L.maxS[n]) return bail(fail(p, MTTKRP_EINVAL, "shard bound"));
         if (hipMemcpyAsync(p->sh(n), shards.data(), shards.size() * 4, hipMemcpyHostToDevice,
                            s) != hipSuccess ||
@@ -916,13 +1047,16 @@ mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable)
     return MTTKRP_OK;
 }
 
-mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms, int64_t *launches)
+mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int kernel, int mode, double *ms,
+                                  int64_t *launches)
 {
     if (!p || !ms || !launches) return fail(p, MTTKRP_EINVAL, "NULL argument");
+    if (kernel != MTTKRP_PROF_MTTKRP && kernel != MTTKRP_PROF_REMAP)
+        return fail(p, MTTKRP_EINVAL, "bad kernel id");
     double tot = 0.0;
     int64_t cnt = 0;
     for (auto &e : p->events) {
-        if (e.a && e.b && (mode < 0 || e.mode == mode)) {
+        if (e.a && e.b && e.kernel == kernel && (mode < 0 || e.mode == mode)) {
             HIPCHK(p, hipEventSynchronize(e.b));
             float t = 0.0f;
             HIPCHK(p, hipEventElapsedTime(&t, e.a, e.b));
@@ -932,7 +1066,7 @@ mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int mode, double *ms, int64_t
     }
     std::vector<ProfEvent> keep;
     for (auto &e : p->events) {
-        if (mode >= 0 && e.mode != mode) {
+        if (e.kernel != kernel || (mode >= 0 && e.mode != mode)) {
             keep.push_back(e);
             continue;
         }

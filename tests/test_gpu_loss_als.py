@@ -16,11 +16,11 @@ LOSS_CASES = [((60, 50, 40), 4000, 16, 51, 64), ((40, 3, 30, 5), 2500, 32, 52, 1
               ((9, 2, 11, 3, 4), 900, 8, 55, 32)]
 
 
-def _loss_case(case):
+def _loss_case(case, flags=0):
     dims, nnz, R, seed, g = case
     t = syn.random_tensor(dims, nnz, R, seed, factors="uniform")
     idx, vals, facs = to_dev(t)
-    return t, Plan(idx, vals, dims, R, g=g), facs
+    return t, Plan(idx, vals, dims, R, g=g, flags=flags), facs
 
 
 def _grad_ref(t, facs64):
@@ -44,10 +44,11 @@ def _grad_ref(t, facs64):
     return refs
 
 
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
 @pytest.mark.parametrize("case", LOSS_CASES)
-def test_loss_and_gradient_match_oracle(case):
-    say("loss case", case)
-    t, p, facs = _loss_case(case)
+def test_loss_and_gradient_match_oracle(case, flags):
+    say("loss case", case, "flags", flags)
+    t, p, facs = _loss_case(case, flags)
     f64 = [f.astype(np.float64) for f in t.factors]
     L_ref, G_ref = oracle.cp_loss_grad(t.dims, t.idx, t.vals, f64)
     p.remap(1 % len(t.dims))                 # start away from L_0

@@ -71,6 +71,8 @@ MTT_CASES = [
     ((2000, 30, 20), 500, 16, 21, True, 0.0, 64),     # many empty rows
     ((50, 40, 30), 37, 16, 22, True, 0.0, 1024),      # nnz < 64
     ((4, 500, 300), 20000, 16, 23, True, 1.5, 64),    # rows over many shards
+    ((3, 200, 100), 150000, 8, 24, False, 0.0, 2),    # ~75K partials: 3 levels
+    ((60, 50, 2, 10, 9), 20000, 16, 25, True, 0.0, 64),  # a 2-index mode
 ]
 
 
@@ -79,12 +81,13 @@ def _oracle_all(t, facs64):
             for n in range(len(t.dims))]
 
 
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
 @pytest.mark.parametrize("case", MTT_CASES)
-def test_mttkrp_all_modes_fp32(case):
+def test_mttkrp_all_modes_fp32(case, flags):
     dims, nnz, R, seed, distinct, zipf, g = case
-    say("mttkrp fp32 case", case)
+    say("mttkrp fp32 case", case, "flags", flags)
     t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
-    p, facs = make_plan(t, g=g)
+    p, facs = make_plan(t, g=g, flags=flags)
     outs = p.mttkrp_all_modes(facs)
     torch.cuda.synchronize()
     assert p.cur_mode == 0
@@ -106,7 +109,7 @@ def test_mttkrp_bf16_factors(case):
     say("mttkrp bf16 case", case)
     t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
     idx, vals, facs = to_dev(t, torch.bfloat16)
-    p = Plan(idx, vals, dims, R, g=g)
+    p = Plan(idx, vals, dims, R, g=g, flags=_abi.FUSED_REMAP if seed % 2 else 0)
     outs = p.mttkrp_all_modes(facs)
     ref32 = _oracle_all(t, t.factors)                        # includes storage error
     refb = _oracle_all(t, [bf16_round(f) for f in t.factors])  # accumulation only
@@ -131,9 +134,10 @@ def test_integer_inputs_bit_exact(dtype):
             assert np.array_equal(outs[n].cpu().numpy().astype(np.float64), ref), (dims, n)
 
 
-def test_single_mode_fused_and_unfused_and_state():
+@pytest.mark.parametrize("extra", [0, _abi.FUSED_REMAP])
+def test_single_mode_fused_and_unfused_and_state(extra):
     t = syn.random_tensor((80, 60, 40, 30), 5000, 16, 41, zipf_s=1.1)
-    p, facs = make_plan(t, g=128, flags=_abi.NO_IMPLICIT_REMAP)
+    p, facs = make_plan(t, g=128, flags=_abi.NO_IMPLICIT_REMAP | extra)
     ref = _oracle_all(t, t.factors)
     out = p.mttkrp_mode(0, facs, fuse_remap=False)
     check_close(out.cpu().numpy(), ref[0][0], ref[0][1], FP32_TOL, "unfused mode 0")
