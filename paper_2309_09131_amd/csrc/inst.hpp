@@ -99,7 +99,12 @@ hipError_t launch_remap<NM>(const uint32_t *rin, uint32_t *rout, const int32_t *
                             int64_t nnz, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-    unsigned grid = (unsigned)((nnz + 255) / 256 < 65536 ? (nnz + 255) / 256 : 65536);
+#ifdef MK_RT
+    const int64_t blocks = (nnz + 256 * MK_RT - 1) / (256 * MK_RT);
+#else
+    const int64_t blocks = (nnz + 2047) / 2048;
+#endif
+    unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
     hipLaunchKernelGGL((remap_kernel<NM>), dim3(grid), dim3(256), 0, s, rin, rout, perm, nnz);
     return hipGetLastError();
 }

@@ -423,13 +423,91 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
 }
 
 // ---- standalone remap: L_{n+1}[P_n[i]] = L_n[i] -------------------------
+// Each block stages RB = 256 * RT consecutive records in LDS, groups them by
+// destination 128-byte line (counting sort on the line number modulo 1024),
+// then stores them in that order, so that records bound for the same line
+// leave in the same store instruction and the L2 combines them into one
+// write.  The result does not depend on the store order (every record has
+// its own destination).
 template <int N>
-__global__ void remap_kernel(const uint32_t *__restrict__ rin, uint32_t *__restrict__ rout,
-                             const int32_t *__restrict__ perm, int64_t nnz)
+__global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__ rin,
+                                                    uint32_t *__restrict__ rout,
+                                                    const int32_t *__restrict__ perm,
+                                                    int64_t nnz)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz;
-         i += (int64_t)gridDim.x * blockDim.x)
-        store_rec<N>(rout, perm[i], load_rec<N>(rin, i));
+#ifdef MK_RT
+    constexpr int RT = MK_RT;
+#else
+    constexpr int RT = 8;                 // records per thread
+#endif
+    constexpr int RB = 256 * RT;
+#ifdef MK_NB
+    constexpr int NB = MK_NB;
+#else
+    constexpr int NB = 1024;              // buckets
+#endif
+    __shared__ Rec<N> srec[RB];
+    __shared__ int32_t sdst[RB];
+    __shared__ int32_t cnt[NB];
+    const int t = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * RB; base < nnz; base += (int64_t)gridDim.x * RB) {
+        for (int k = t; k < NB; k += 256) cnt[k] = 0;
+        __syncthreads();
+        Rec<N> r[RT];
+        int32_t d[RT], pos[RT];
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int64_t i = base + k * 256 + t;
+            const bool ok = i < nnz;
+            r[k] = load_rec<N>(rin, ok ? i : 0);
+            d[k] = ok ? perm[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int b = (d[k] >= 0) ? (int)(((int64_t)d[k] * (N + 1) / 32) & (NB - 1)) : NB - 1;
+            pos[k] = atomicAdd(&cnt[b], 1);   // LDS atomic: slot within bucket
+            d[k] = (d[k] >= 0) ? d[k] : -1;
+            pos[k] |= b << 16;
+        }
+        __syncthreads();
+        // exclusive scan of the bucket counts (4 per thread, then across)
+        {
+            static_assert(NB == 1024, "scan assumes 4 buckets per thread");
+            int c0 = cnt[4 * t], c1 = cnt[4 * t + 1], c2 = cnt[4 * t + 2], c3 = cnt[4 * t + 3];
+            int s = c0 + c1 + c2 + c3, x = s;
+            const int lane = t & 63, w = t >> 6;
+#pragma unroll
+            for (int dd = 1; dd < 64; dd <<= 1) {
+                const int y = __shfl_up(x, dd);
+                if (lane >= dd) x += y;
+            }
+            __shared__ int wsum[4];
+            if (lane == 63) wsum[w] = x;
+            __syncthreads();
+            int off = 0;
+            for (int k = 0; k < w; ++k) off += wsum[k];
+            int e = off + x - s;
+            cnt[4 * t] = e; e += c0;
+            cnt[4 * t + 1] = e; e += c1;
+            cnt[4 * t + 2] = e; e += c2;
+            cnt[4 * t + 3] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int slot = cnt[pos[k] >> 16] + (pos[k] & 0xffff);
+            srec[slot] = r[k];
+            sdst[slot] = d[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const int slot = k * 256 + t;
+            const int32_t dst = sdst[slot];
+            if (dst >= 0) store_rec<N>(rout, dst, srec[slot]);
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace mk
