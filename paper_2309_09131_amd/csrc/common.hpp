@@ -10,14 +10,21 @@
 // Packed with 4-byte alignment; gfx950 global loads/stores of 16 bytes only
 // need dword alignment, so the compiler emits dwordx4 (+dword/dwordx2).
 template <int N>
-struct __attribute__((packed, aligned(4))) Rec {
+struct Rec {
     uint32_t w[N + 1];
 };
 
 template <int N>
 __device__ __forceinline__ Rec<N> load_rec(const uint32_t *__restrict__ buf, int64_t i)
 {
-    return *reinterpret_cast<const Rec<N> *>(buf + i * (N + 1));
+    // word by word: keeps the record in registers (a struct copy through a
+    // reinterpreted pointer made the compiler stage record arrays in LDS);
+    // adjacent dwords are still merged into wide loads
+    Rec<N> r;
+    const uint32_t *p = buf + i * (N + 1);
+#pragma unroll
+    for (int k = 0; k < N + 1; ++k) r.w[k] = p[k];
+    return r;
 }
 
 template <int N>
@@ -50,10 +57,12 @@ __device__ __forceinline__ void store_rec_nt(uint32_t *__restrict__ buf, int64_t
 template <int N>
 __device__ __forceinline__ int rec_coord(const Rec<N> &r, int n)
 {
-    int v = (int)r.w[0];
+    // masks instead of selects: a select chain over loaded words gets folded
+    // into a select of addresses, which forces the record into memory
+    uint32_t v = 0;
 #pragma unroll
-    for (int k = 1; k < N; ++k) v = (n == k) ? (int)r.w[k] : v;
-    return v;
+    for (int k = 0; k < N; ++k) v |= r.w[k] & (0u - (uint32_t)(n == k));
+    return (int)v;
 }
 
 // bfloat16 storage <-> float.  Widening is exact (the 16 high bits).

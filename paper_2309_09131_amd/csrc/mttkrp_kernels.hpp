@@ -254,6 +254,20 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
 
     const Inputs<N> in(a, n);
     const int fsub = ract ? sub : 0;             // in-range lane for loads
+    // Records are loaded once per lane group, not once per lane: lane `sub`
+    // of a slot loads records sub, sub + LANES, ... of the slot's next U
+    // nonzeros (RPL per lane), and the words are then broadcast inside the
+    // slot with cross-lane moves.  The vector-memory address unit is the
+    // limiter of this kernel, so duplicate loads are expensive.  The next
+    // group's records are loaded while the current group computes.
+    constexpr int RPL = (U + LANES - 1) / LANES;
+    Rec<N> nxt[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const int u = sub + j * LANES;
+        const int e = s0 + u;
+        nxt[j] = load_rec<N>(a.rin, (u < U && u < run && e < end) ? e : start);
+    }
     for (int k = 0; k < run; k += U) {           // uniform trip count
         Rec<N> rc[U];
         bool ok[U];
@@ -261,11 +275,16 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
         for (int u = 0; u < U; ++u) {
             const int e = s0 + k + u;
             ok[u] = (k + u < run) && (e < end);
-#ifdef MK_NT_REC
-            rc[u] = load_rec_nt<N>(a.rin, ok[u] ? e : start);
-#else
-            rc[u] = load_rec<N>(a.rin, ok[u] ? e : start);   // clamped, no branch
-#endif
+            const int src = slot * LANES + (u % LANES);
+#pragma unroll
+            for (int w = 0; w < N + 1; ++w)
+                rc[u].w[w] = (uint32_t)__shfl((int)nxt[u / LANES].w[w], src);
+        }
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {            // clamped index: no branch
+            const int u = sub + j * LANES;
+            const int e = s0 + k + U + u;
+            nxt[j] = load_rec<N>(a.rin, (u < U && k + U + u < run && e < end) ? e : start);
         }
         float pr[U][V];
         float mm[U];

@@ -383,15 +383,19 @@ static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 static mk::LaneCfg lane_cfg(int R, mttkrp_dtype fdt, const void *const *facs, int N,
                             const float *out)
 {
-    // 32 bytes of factor row per lane when R allows it (measured fastest on
-    // gfx950: fewer lanes repeat each record load), else 16 bytes, else the
-    // strided form for ranks that are not multiples of the vector width
-    const int V16 = (fdt == MTTKRP_BF16) ? 8 : 4;
+    // Lanes per nonzero = R / 8 when possible: FP32 rows are then read 32
+    // bytes per lane (two 16-byte loads), BF16 rows 16 bytes per lane.  The
+    // vector-memory address unit limits this kernel, and this choice issues
+    // the fewest load instructions per nonzero.  Otherwise 16-byte lanes,
+    // else the strided form for ranks that are not a multiple of the vector
+    // width.
+    const bool bf = fdt == MTTKRP_BF16;
+    const int V16 = bf ? 8 : 4;                  // elements per 16 bytes
     bool ok = (R % V16 == 0) && (out == nullptr || aligned16(out));
     for (int w = 0; w < N && ok; ++w)
         if (facs[w] && !aligned16(facs[w])) ok = false;
-    if (ok && R % (2 * V16) == 0 && next_pow2(R / (2 * V16)) <= 32)
-        return mk::LaneCfg{next_pow2(R / (2 * V16)), 2, false};
+    if (ok && !bf && R % 8 == 0 && next_pow2(R / 8) <= 32)
+        return mk::LaneCfg{next_pow2(R / 8), 2, false};
     if (ok && next_pow2(R / V16) <= 64) return mk::LaneCfg{next_pow2(R / V16), 1, false};
     return mk::LaneCfg{64, (R + 63) / 64, true};
 }
