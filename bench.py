@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
-"""All-mode sparse MTTKRP sweep benchmark on one MI355X.
+"""All-mode sparse MTTKRP benchmark on one MI355X.
 
-Workload (default): 3-mode COO tensor 50000 x 40000 x 30000, 20M distinct
-nonzeros with Zipf(1.2) coordinates over shuffled indices, lognormal(0,1)
-values, rank 32, N(0,1) FP32 factors; one step = MTTKRP along all three
-modes, each followed by the dynamic remap into the next mode's layout (the
-tensor ends where it started).
+Default workload (--config 2): a 3-mode COO tensor 50000 x 40000 x 30000
+with 20M distinct nonzeros (Zipf(1.2) coordinates over shuffled indices,
+lognormal(0,1) values), rank 32, N(0,1) FP32 factors.  One step is MTTKRP
+along all three modes, each followed by the dynamic remap of the tensor into
+the next mode's layout; the tensor ends where it started.
 
-Reports one JSON line: whole-sweep algorithmic bytes / sweep time (GB/s),
-sweep ms, the per-mode kernel's roofline fraction against 8 TB/s HBM, the
-BF16-stored-factor sweep (speedup and errors against the FP64 oracle on
-sampled rows), and the FP64 oracle timed on one host core.
+Other workloads (explicit runs; parity and reporting, not the headline):
+  --config 1  1000x800x600, 100K nnz, R=16: sweep + one CP-ALS sweep
+  --config 3  1e6x5e5x2e4x2e3, 100M nnz, R=32: FP32 and BF16 sweeps
+  --config 4  2e5^3, 50M nnz planted rank 64: sampled CP loss forward +
+              autograd backward, finite differences on a 10K subsample
+  --config 5  2e6x1e6x1e5x5e3x500, 200M nnz, R=16: full CP-ALS sweep, FP32
+              and BF16
 
-  python bench.py [--steps K] [--warmup W] [--config 2] [--no-cpu-baseline]
+Prints one JSON line (see the design doc for every field).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,47 +29,47 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-
 METRIC = "all-mode spMTTKRP sweep ms & HBM GB/s; BF16 vs FP32 speedup at stated error"
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------- byte models
+def rec_bytes(N):
+    return 4 * N + 4
+
+
 def b_alg_mode(dims, nnz, R, n, sf):
-    """Algorithmic bytes of one mode in the paper's traffic model: record read
-    + remap write + gathered input-factor rows + output write."""
+    """Paper traffic model for one mode: record read + remap write +
+    gathered input-factor rows + output write."""
     N = len(dims)
-    E = 4 * N + 4
-    return nnz * E * 2 + nnz * (N - 1) * R * sf + dims[n] * R * 4
+    return nnz * rec_bytes(N) * 2 + nnz * (N - 1) * R * sf + dims[n] * R * 4
 
 
 def b_alg_mttkrp_kernel(dims, nnz, R, n, sf):
-    """Algorithmic bytes of one launch of the per-mode MTTKRP kernel (remap
-    done by its own kernel): record read + gathers + output write."""
+    """One launch of the per-mode MTTKRP kernel: records + gathers + output."""
     N = len(dims)
-    return nnz * (4 * N + 4) + nnz * (N - 1) * R * sf + dims[n] * R * 4
+    return nnz * rec_bytes(N) + nnz * (N - 1) * R * sf + dims[n] * R * 4
 
 
 def b_alg_remap_kernel(dims, nnz):
     """Record read + remap-target read + record write."""
-    E = 4 * len(dims) + 4
-    return nnz * (2 * E + 4)
+    return nnz * (2 * rec_bytes(len(dims)) + 4)
 
 
 def b_min_mttkrp_kernel(dims, nnz, R, n, sf):
     """Compulsory bytes: every record once, every input factor once, output."""
     N = len(dims)
-    return nnz * (4 * N + 4) + sum(dims[w] * R * sf for w in range(N) if w != n) \
+    return nnz * rec_bytes(N) + sum(dims[w] * R * sf for w in range(N) if w != n) \
         + dims[n] * R * 4
 
 
 def source_sha():
-    import hashlib
     h = hashlib.sha256()
-    here = os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                        "paper_2309_09131_amd", "csrc")
+    here = os.path.join(ROOT, "paper_2309_09131_amd", "csrc")
     for f in ("common.hpp", "mttkrp_kernels.hpp", "inst.hpp", "launch.hpp"):
         with open(os.path.join(here, f), "rb") as fh:
             h.update(fh.read())
@@ -90,35 +94,55 @@ def counter_traffic(path, key):
         return None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--g", type=int, default=0)
-    ap.add_argument("--natural-order", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true")
-    ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the fused-remap ablation sweep")
-    ap.add_argument("--copy-calib-mb", type=int, default=256,
-                    help="size of a plain device copy run for counter calibration")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
-              "path (the sharding design is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------- helpers
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
 
-    import torch
-    from paper_2309_09131_amd import _abi
-    from paper_2309_09131_amd import synthetic as syn
-    from paper_2309_09131_amd.api import Plan
+    def __call__(self, fn, steps, warm):
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
 
-    dev = torch.device("cuda:0")
+
+def sampled_rows(T, rng, heavy=4, rand=28):
+    out = []
+    for n in range(T.nmodes):
+        counts = np.bincount(T.idx[n], minlength=T.dims[n])
+        top = np.argsort(counts)[-heavy:]
+        r = rng.choice(T.dims[n], min(rand, T.dims[n]), replace=False)
+        out.append(np.unique(np.concatenate([top, r])))
+    return out
+
+
+def error_report(oracle, T, factors64, outs, samples, torch, dev):
+    """Per mode: normwise and |.|-scaled elementwise error on sampled rows
+    against the FP64 oracle (each sampled row computed one by one)."""
+    rep = []
+    for n in range(T.nmodes):
+        ref, rabs = oracle.mttkrp_rows(T.dims, T.idx, T.vals, factors64, n, samples[n])
+        got = outs[n][torch.from_numpy(samples[n]).to(dev)].cpu().numpy().astype(np.float64)
+        nw = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+        el = float(np.max(np.abs(got - ref) / np.where(rabs > 0, rabs, 1)))
+        rep.append({"normwise": nw, "elementwise_vs_abs": el,
+                    "max_abs": float(np.abs(got - ref).max())})
+    return rep
+
+
+# ---------------------------------------------------------------- MTTKRP sweep
+def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
     w = syn.WORKLOADS[args.config]
     t0 = time.time()
-    T = syn.generate(args.config)
+    T = syn.generate(args.config, progress=log)
     log(f"generated {w.name}: nnz={T.nnz} in {time.time() - t0:.1f}s")
     dims, R, N, nnz = T.dims, T.rank, T.nmodes, T.nnz
     idx = torch.from_numpy(T.idx).to(dev)
@@ -131,10 +155,10 @@ def main():
     plan = Plan(idx, vals, dims, R, g=args.g, flags=flags)
     torch.cuda.synchronize()
     plan_ms = (time.time() - tp) * 1e3
-    del idx, vals
     log(f"plan {plan_ms:.1f} ms; shards per mode "
         f"{[plan.info(_abi.INFO_NSHARDS, n) for n in range(N)]}")
     outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in dims]
+    timer = Timer(torch)
 
     # a plain copy of known size (counter calibration for FETCH/WRITE_SIZE)
     if args.copy_calib_mb > 0:
@@ -145,29 +169,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def timed(factors, steps, warm):
-        for _ in range(warm):
-            plan.mttkrp_all_modes(factors, outs)
-        torch.cuda.synchronize()
+    def timed(factors):
         plan.profile(True)
-        plan.profile_read(_abi.PROF_MTTKRP)      # reset
-        plan.profile_read(_abi.PROF_REMAP)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(steps):
+        for _ in range(args.warmup):
             plan.mttkrp_all_modes(factors, outs)
-        e1.record()
         torch.cuda.synchronize()
-        sweep_ms = e0.elapsed_time(e1) / steps
+        plan.profile_read(_abi.PROF_MTTKRP)      # drop warm-up launches
+        plan.profile_read(_abi.PROF_REMAP)
+        ms = timer(lambda: plan.mttkrp_all_modes(factors, outs), args.steps, 0)
         per_mode = [plan.profile_read(_abi.PROF_MTTKRP, n) for n in range(N)]
         per_remap = [plan.profile_read(_abi.PROF_REMAP, n) for n in range(N)]
         plan.profile(False)
-        return sweep_ms, per_mode, per_remap
+        return ms, per_mode, per_remap
 
-    sweep_ms, per_mode, per_remap = timed(f32, args.steps, args.warmup)
-    log(f"fp32 sweep {sweep_ms:.3f} ms; per-mode MTTKRP kernel ms "
+    sweep_ms, per_mode, per_remap = timed(f32)
+    log(f"fp32 sweep {sweep_ms:.3f} ms; MTTKRP kernel ms "
         f"{[round(m / max(c, 1), 4) for m, c in per_mode]}; remap kernel ms "
         f"{[round(m / max(c, 1), 4) for m, c in per_remap]}")
     sweep_bytes = sum(b_alg_mode(dims, nnz, R, n, 4) for n in range(N))
@@ -183,82 +199,72 @@ def main():
     mk_ms, mk_bytes, mk_gbs = kstats(per_mode, lambda n: b_alg_mttkrp_kernel(dims, nnz, R, n, 4))
     rm_ms, rm_bytes, rm_gbs = kstats(per_remap, lambda n: b_alg_remap_kernel(dims, nnz))
     mk_min = sum(b_min_mttkrp_kernel(dims, nnz, R, n, 4) for n in range(N)) / N
-    prof_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
-    ctr = os.path.join(prof_dir, f"mttkrp_kernel_{w.name}_counters.txt")
+    ctr = os.path.join(ROOT, "profiles", f"mttkrp_kernel_{w.name}_counters.txt")
     fetch = counter_traffic(ctr, "fetch_bytes_per_launch")
     write = counter_traffic(ctr, "write_bytes_per_launch")
     traffic = (fetch + write) if (fetch is not None and write is not None) else None
 
-    # errors on sampled rows against the FP64 oracle (FP32, then BF16)
-    import oracle  # test infrastructure: error report and CPU baseline only
     rng = np.random.default_rng(0)
-    samples = []
-    for n in range(N):
-        counts = np.bincount(T.idx[n], minlength=dims[n])
-        heavy = np.argsort(counts)[-4:]
-        rnd = rng.choice(dims[n], 28, replace=False)
-        samples.append(np.unique(np.concatenate([heavy, rnd])))
-
-    def errors(outs_t):
-        rep = []
-        for n in range(N):
-            ref, rabs = oracle.mttkrp_rows(dims, T.idx, T.vals, T.factors, n, samples[n])
-            got = outs_t[n][torch.from_numpy(samples[n]).to(dev)].cpu().numpy().astype(np.float64)
-            nw = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-            el = float(np.max(np.abs(got - ref) / np.where(rabs > 0, rabs, 1)))
-            rep.append({"normwise": nw, "elementwise_vs_abs": el,
-                        "max_abs": float(np.abs(got - ref).max())})
-        return rep
-
+    samples = sampled_rows(T, rng)
     plan.mttkrp_all_modes(f32, outs)
     torch.cuda.synchronize()
-    err32 = errors(outs)
+    err32 = error_report(oracle, T, T.factors, outs, samples, torch, dev)
+
     result_bf16 = None
     if not args.no_bf16:
-        bms, bmode, bremap = timed(bf, args.steps, args.warmup)
+        bms, bmode, bremap = timed(bf)
         plan.mttkrp_all_modes(bf, outs)
         torch.cuda.synchronize()
-        errb = errors(outs)
+        errb = error_report(oracle, T, T.factors, outs, samples, torch, dev)
         bbytes = sum(b_alg_mode(dims, nnz, R, n, 2) for n in range(N))
         result_bf16 = {"sweep_ms": round(bms, 4), "speedup_vs_fp32": round(sweep_ms / bms, 3),
                        "alg_GBs": round(bbytes / (bms * 1e-3) / 1e9, 1),
+                       "mttkrp_kernel_ms": [round(m / max(c, 1), 4) for m, c in bmode],
                        "error_vs_fp64_oracle": errb, "tolerance": 2e-2}
         log(f"bf16 sweep {bms:.3f} ms (x{sweep_ms / bms:.2f})")
 
-    def fused_sweep():
-        fplan = Plan(torch.from_numpy(T.idx).to(dev), torch.from_numpy(T.vals).to(dev), dims,
-                     R, g=args.g, flags=flags | _abi.FUSED_REMAP)
-        for _ in range(args.warmup):
-            fplan.mttkrp_all_modes(f32, outs)
-        torch.cuda.synchronize()
-        fe0 = torch.cuda.Event(enable_timing=True)
-        fe1 = torch.cuda.Event(enable_timing=True)
-        fe0.record()
-        for _ in range(args.steps):
-            fplan.mttkrp_all_modes(f32, outs)
-        fe1.record()
-        torch.cuda.synchronize()
-        fused_ms = fe0.elapsed_time(fe1) / args.steps
-        del fplan
-        return fused_ms
-
-    # ablation: remap inside the MTTKRP kernel (the paper's same-agent form)
     fused_ms = None
     if not args.no_ablation:
-        fused_ms = fused_sweep()
-    log(f"fused-remap fp32 sweep {fused_ms} ms")
+        # the paper's same-agent form: remap written from inside the MTTKRP kernel
+        fplan = Plan(idx, vals, dims, R, g=args.g, flags=flags | _abi.FUSED_REMAP)
+        fused_ms = timer(lambda: fplan.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
+        del fplan
+        log(f"fused-remap fp32 sweep {fused_ms:.3f} ms")
 
+    als = None
+    if args.config in (1, 5):
+        als = {}
+        for name, F in (("fp32", f32), ("bf16", bf)):
+            fac = [f.clone() for f in F]
+            lam = torch.empty(R, dtype=torch.float64, device=dev)
+            mbuf = torch.empty((max(dims), R), dtype=torch.float32, device=dev)
+            steps = max(1, min(args.steps, 5))
+            ms = timer(lambda: plan.cp_als_sweep(fac, mbuf, lam), steps, 1)
+            fac = [f.clone() for f in F]
+            lam, fit = plan.cp_als_sweep(fac, mbuf, lam)
+            als[name] = {"sweep_ms": round(ms, 3), "fit_after_one_sweep": float(fit.item())}
+            log(f"CP-ALS sweep {name}: {ms:.3f} ms, fit {fit.item():.6f}")
+        if nnz <= 2_000_000:
+            _, olam, ofit, _, _ = oracle.cp_als_sweep(dims, T.idx, T.vals, T.factors)
+            als["oracle_fit"] = ofit
+        als["bf16_speedup_vs_fp32"] = round(als["fp32"]["sweep_ms"] / als["bf16"]["sweep_ms"], 3)
+
+    del idx, vals
     cpu = None
     if not args.no_cpu_baseline:
+        # the FP64 oracle on one core, on a bounded sample of the same tensor
+        S = min(nnz, args.cpu_sample)
         tc = time.time()
         for n in range(N):
-            oracle.mttkrp(dims, T.idx, T.vals, T.factors, n)
+            oracle.mttkrp(dims, T.idx[:, :S], T.vals[:S], T.factors, n)
         cs = time.time() - tc
-        cpu = {"value": round(sweep_bytes / cs / 1e9, 4), "unit": "GB/s", "cores": 1,
-               "kind": "oracle", "sweep_s": round(cs, 2),
-               "sample": f"full workload: FP64 oracle MTTKRP along all {N} modes "
-                         f"over all {nnz} nonzeros, single thread"}
-        log(f"oracle sweep {cs:.1f} s on one core")
+        sb = sum(b_alg_mode(dims, S, R, n, 4) for n in range(N))
+        what = "all" if S == nnz else f"the first {S} (in generation order) of {nnz}"
+        cpu = {"value": round(sb / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sweep_s": round(cs, 2),
+               "sample": f"FP64 oracle MTTKRP along all {N} modes over {what} nonzeros, "
+                         f"single thread; value = paper-model bytes of that sample / time"}
+        log(f"oracle sweep {cs:.1f} s on one core ({S} nonzeros)")
 
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s",
@@ -291,7 +297,142 @@ def main():
         "fp32_error_vs_fp64_oracle": err32,
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
+        "cp_als": als,
     }
+    return rec
+
+
+# ---------------------------------------------------------------- CP loss
+def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
+    from paper_2309_09131_amd.api import cp_loss
+    w = syn.WORKLOADS[4]
+    t0 = time.time()
+    T = syn.generate(4, progress=log)
+    log(f"generated {w.name}: nnz={T.nnz} in {time.time() - t0:.1f}s")
+    dims, R, N, nnz = T.dims, T.rank, T.nmodes, T.nnz
+    idx = torch.from_numpy(T.idx).to(dev)
+    vals = torch.from_numpy(T.vals).to(dev)
+    tp = time.time()
+    plan = Plan(idx, vals, dims, R, g=args.g)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - tp) * 1e3
+    timer = Timer(torch)
+    fac = [torch.from_numpy(f).to(dev).requires_grad_(True) for f in T.factors]
+
+    def step():
+        for f in fac:
+            f.grad = None
+        loss = cp_loss(plan, fac)
+        loss.backward()
+        return loss
+
+    ms = timer(step, args.steps, args.warmup)
+    fwd_ms = timer(lambda: plan.cp_loss_grad(fac, loss=True, grads=False), args.steps, 1)
+    E = rec_bytes(N)
+    fwd_b = nnz * (E + N * R * 4)
+    bwd_b = sum(nnz * (2 * E + N * R * 4) + dims[k] * R * 4 for k in range(N))
+    value = (fwd_b + bwd_b) / (ms * 1e-3) / 1e9
+    log(f"loss fwd+bwd {ms:.3f} ms (fwd {fwd_ms:.3f} ms)")
+
+    # checks on a 10K-nonzero subsample (first in generation order)
+    S = 10_000
+    sub_idx = np.ascontiguousarray(T.idx[:, :S])
+    sub_val = np.ascontiguousarray(T.vals[:S])
+    sp = Plan(torch.from_numpy(sub_idx).to(dev), torch.from_numpy(sub_val).to(dev), dims, R,
+              g=256)
+    f64 = [f.astype(np.float64) for f in T.factors]
+    L_ref, G_ref = oracle.cp_loss_grad(dims, sub_idx, sub_val, f64)
+    sf = [torch.from_numpy(f).to(dev) for f in T.factors]
+    l_gpu, g_gpu = sp.cp_loss_grad(sf)
+    loss_rel = abs(l_gpu.item() - L_ref) / abs(L_ref)
+    grad_rel = max(float(np.linalg.norm(g_gpu[k].cpu().numpy() - G_ref[k])
+                         / np.linalg.norm(G_ref[k])) for k in range(N))
+    rng = np.random.default_rng(1)
+    fd_gpu, fd_orc = [], []
+    for _ in range(16):
+        k = int(rng.integers(0, N))
+        i = int(rng.choice(sub_idx[k]))
+        r = int(rng.integers(0, R))
+        h = 0.25                       # exact: the loss is quadratic per entry
+        fp = [f.clone() for f in sf]
+        fm = [f.clone() for f in sf]
+        fp[k][i, r] += h
+        fm[k][i, r] -= h
+        lp = sp.cp_loss_grad(fp, grads=False)[0].item()
+        lm = sp.cp_loss_grad(fm, grads=False)[0].item()
+        g = g_gpu[k][i, r].item()
+        fd_gpu.append(abs((lp - lm) / (2 * h) - g) / max(1.0, abs(g)))
+        hp = [f.copy() for f in f64]
+        hm = [f.copy() for f in f64]
+        hp[k][i, r] += 1e-3
+        hm[k][i, r] -= 1e-3
+        fdo = (oracle.cp_loss_grad(dims, sub_idx, sub_val, hp, want_grad=False)
+               - oracle.cp_loss_grad(dims, sub_idx, sub_val, hm, want_grad=False)) / 2e-3
+        fd_orc.append(abs(fdo - G_ref[k][i, r]) / max(1.0, abs(G_ref[k][i, r])))
+    # loss at the planted truth: expected nnz * sigma^2
+    truth = [torch.from_numpy(T.extra[f"true{n}"]).to(dev) for n in range(N)]
+    l_true = plan.cp_loss_grad(truth, grads=False)[0].item()
+    sigma = float(T.extra["sigma"])
+    checks = {"subsample_nnz": S, "loss_rel_err_vs_oracle": loss_rel,
+              "grad_normwise_rel_err_vs_oracle": grad_rel,
+              "fd_vs_gpu_grad_max_rel": max(fd_gpu), "fd_vs_oracle_grad_max_rel": max(fd_orc),
+              "loss_at_truth": l_true, "expected_nnz_sigma2": nnz * sigma ** 2}
+    log(f"checks {checks}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        Sc = min(nnz, args.cpu_sample // 8)
+        tc = time.time()
+        oracle.cp_loss_grad(dims, T.idx[:, :Sc], T.vals[:Sc], f64)
+        cs = time.time() - tc
+        sb = Sc * (E + N * R * 4) + N * Sc * (2 * E + N * R * 4)
+        cpu = {"value": round(sb / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle loss + gradient over the first {Sc} of {nnz} nonzeros, "
+                         f"single thread", "seconds": round(cs, 2)}
+    return {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(dims), "nnz": nnz, "rank": R,
+                   "step": "sampled CP loss forward + autograd backward to all factors",
+                   "plan_ms": round(plan_ms, 1)},
+        "roofline": None, "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
+        "checks": checks,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--g", type=int, default=0)
+    ap.add_argument("--natural-order", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the fused-remap ablation sweep")
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000,
+                    help="nonzeros the CPU oracle baseline processes at most")
+    ap.add_argument("--copy-calib-mb", type=int, default=256,
+                    help="size of a plain device copy run for counter calibration")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
+              "path (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import oracle  # test infrastructure: error report and CPU baseline only
+    from paper_2309_09131_amd import _abi
+    from paper_2309_09131_amd import synthetic as syn
+    from paper_2309_09131_amd.api import Plan
+
+    dev = torch.device("cuda:0")
+    fn = bench_loss if args.config == 4 else bench_sweep
+    rec = fn(args, torch, dev, syn, _abi, Plan, oracle)
     print(json.dumps(rec), flush=True)
 
 

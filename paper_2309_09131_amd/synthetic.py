@@ -140,7 +140,7 @@ def _zipf_cdf(n: int, s: float) -> np.ndarray:
     return cdf
 
 
-def draw_coordinates(rng, dims, target, kind, s=0.0, batch=BATCH):
+def draw_coordinates(rng, dims, target, kind, s=0.0, batch=BATCH, progress=None):
     """Steps 1-3 of the recipe: distinct coordinate tuples, draw order."""
     N = len(dims)
     perms, cdfs = [], []
@@ -164,10 +164,14 @@ def draw_coordinates(rng, dims, target, kind, s=0.0, batch=BATCH):
     while total < target:
         one_batch()
         total += batch
+        if progress:
+            progress(f"drew {total} coordinate tuples")
     while True:
         cols = [np.concatenate(c) if len(c) > 1 else c[0] for c in chunks]
         chunks = [[c] for c in cols]
         keep = dedupe_first(cols)
+        if progress:
+            progress(f"{keep.shape[0]} distinct of {total} drawn (target {target})")
         if keep.shape[0] >= target:
             keep = keep[:target]
             return np.stack([c[keep] for c in cols]).astype(np.int32)
@@ -194,7 +198,7 @@ def _planted_values(idx, factors, chunk=1 << 20):
 
 def generate(cfg: int, nnz: int | None = None, dims: tuple | None = None,
              rank: int | None = None, batch: int = BATCH,
-             cache_dir: str | None = None) -> Tensor:
+             cache_dir: str | None = None, progress=None) -> Tensor:
     """Build workload `cfg` (1..5); nnz/dims/rank override for scaled cases."""
     w = WORKLOADS[cfg]
     dims = tuple(int(d) for d in (dims or w.dims))
@@ -213,7 +217,7 @@ def generate(cfg: int, nnz: int | None = None, dims: tuple | None = None,
                     t.extra[k[2:]] = z[k]
             return t
     rng = np.random.Generator(np.random.PCG64(w.seed))
-    idx = draw_coordinates(rng, dims, nnz, w.coords, w.zipf_s, batch)
+    idx = draw_coordinates(rng, dims, nnz, w.coords, w.zipf_s, batch, progress)
     extra = {}
     if w.values == "lognormal":
         vals = rng.lognormal(0.0, 1.0, nnz).astype(np.float32)
