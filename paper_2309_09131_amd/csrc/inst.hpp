@@ -99,12 +99,12 @@ hipError_t launch_remap<NM>(const uint32_t *rin, uint32_t *rout, const int32_t *
                             int64_t nnz, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-#ifdef MK_RT
-    const int64_t blocks = (nnz + 256 * MK_RT - 1) / (256 * MK_RT);
-#else
-    const int64_t blocks = (nnz + 2047) / 2048;
-#endif
-    unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
+    // one block per chunk of 256 * RT records (RT as in remap_kernel), the
+    // grid rounded up to a multiple of the 8 XCDs
+    constexpr int RTC = (96 * 1024) / (256 * (4 * (NM + 1) + 4));
+    constexpr int RT = 16 < RTC ? 16 : RTC;
+    const int64_t nchunks = (nnz + 256 * RT - 1) / (256 * RT);
+    unsigned grid = (unsigned)(((nchunks + 7) / 8) * 8);
     hipLaunchKernelGGL((remap_kernel<NM>), dim3(grid), dim3(256), 0, s, rin, rout, perm, nnz);
     return hipGetLastError();
 }

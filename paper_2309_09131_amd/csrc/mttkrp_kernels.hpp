@@ -442,7 +442,8 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
 }
 
 // ---- standalone remap: L_{n+1}[P_n[i]] = L_n[i] -------------------------
-// Each block stages RB = 256 * RT consecutive records in LDS, groups them by
+// Each block stages one chunk of RB = 256 * RT consecutive records in LDS (RT = 16,
+// fewer for wide records so the stage stays within 96 KB), groups them by
 // destination 128-byte line (counting sort on the line number modulo 1024),
 // then stores them in that order, so that records bound for the same line
 // leave in the same store instruction and the L2 combines them into one
@@ -455,10 +456,13 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
                                                     int64_t nnz)
 {
 #ifdef MK_RT
-    constexpr int RT = MK_RT;
+    constexpr int RT0 = MK_RT;
 #else
-    constexpr int RT = 8;                 // records per thread
+    constexpr int RT0 = 16;               // records per thread
 #endif
+    // keep the LDS stage within 96 KB for wide records
+    constexpr int RTC = (96 * 1024) / (256 * (4 * (N + 1) + 4));
+    constexpr int RT = RT0 < RTC ? RT0 : RTC;
     constexpr int RB = 256 * RT;
 #ifdef MK_NB
     constexpr int NB = MK_NB;
@@ -469,7 +473,16 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
     __shared__ int32_t sdst[RB];
     __shared__ int32_t cnt[NB];
     const int t = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * RB; base < nnz; base += (int64_t)gridDim.x * RB) {
+    // XCD-aware chunk order: workgroups are handed to the 8 XCDs round-robin,
+    // so block b takes chunk (b % 8) * per + b / 8 and every XCD walks one
+    // contiguous range of the tensor.  Records that share a destination line
+    // come from neighbouring chunks (consecutive output rows of this mode),
+    // so their partial-line writes meet, and combine, in the same L2.
+    const int64_t nchunks = (nnz + RB - 1) / RB;
+    const int64_t per = (nchunks + 7) / 8;
+    const int64_t chunk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (chunk < nchunks) {
+        const int64_t base = chunk * RB;
         for (int k = t; k < NB; k += 256) cnt[k] = 0;
         __syncthreads();
         Rec<N> r[RT];

@@ -22,6 +22,10 @@ namespace {
 constexpr int DEFAULT_G = 1024;
 constexpr int DEFAULT_WORKERS = 256;
 constexpr int GRAM_TARGET_BLOCKS = 1024;
+constexpr int SEG_VALS = 8192;        // floats a segmented-reduction block stages
+
+// entries per segmented-reduction block
+int seg_block(int R) { return std::min(256, SEG_VALS / R); }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -113,7 +117,8 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     L->rt_gpart = rtake((size_t)GRAM_TARGET_BLOCKS * 256 * 8 + (size_t)R * R * 8);
     L->rt_colsq = rtake((size_t)als::APPLY_BLOCKS * R * 8);
     L->rt_lambda_tmp = rtake((size_t)R * 8 + 64);
-    const int64_t seg_entries = maxS / 64 + 8;     // >= 2 * ceil(2 * maxS / 256)
+    // level 0 has at most 2*maxS entries; each level emits 2 per block
+    const int64_t seg_entries = 2 * ((2 * maxS + seg_block(R) - 1) / seg_block(R)) + 8;
     L->rt_seg[0] = rtake((size_t)seg_entries * R * 4);
     L->rt_seg[1] = rtake((size_t)seg_entries * R * 4);
     L->rt_segk[0] = rtake((size_t)seg_entries * 4);
@@ -258,16 +263,16 @@ __global__ void fill_zero_kernel(float *__restrict__ p, int64_t n)
 // Deterministic segmented reduction of the shard boundary partials of rows
 // split across shards (one level).  Entries are R-float vectors with sorted
 // row keys (level 0: read through `ids` from the per-shard partial slots).
-// Block b takes entries [b*SEG_B, (b+1)*SEG_B): slots of RL lanes walk runs
-// in order; rows wholly inside the block are written to `out`; the block's
-// first and last rows go to the next level as two entries (or to `out`
-// when this is the last level).  Fixed partition and order: bit-exact reruns.
-constexpr int SEG_B = 256;
+// Block b takes entries [b*B, (b+1)*B), B = seg_block(R): they are first
+// staged in LDS with coalesced loads; then slots of RL lanes walk runs in
+// order; rows wholly inside the block are written to `out`; the block's
+// first and last rows go to the next level as two entries (or to `out` when
+// this is the last level).  Fixed partition and order: bit-exact reruns.
 
 __global__ __launch_bounds__(256) void seg_reduce_kernel(const float *__restrict__ src,
                                                          const int32_t *__restrict__ ids,
                                                          const int32_t *__restrict__ keys,
-                                                         int64_t P, int R, int RL,
+                                                         int64_t P, int B, int R, int RL,
                                                          float *__restrict__ out,
                                                          float *__restrict__ next,
                                                          int32_t *__restrict__ next_keys,
@@ -275,24 +280,53 @@ __global__ __launch_bounds__(256) void seg_reduce_kernel(const float *__restrict
 {
     __shared__ int32_t s_head[256], s_tail[256], s_single[256];
     __shared__ float s_hsum[2 * 256];          // [SL][R] heads, then tails (SL*R <= 256)
+    __shared__ float s_val[SEG_VALS];
+    __shared__ int32_t s_key[256];
     const int SL = 256 / RL;
     const int r = threadIdx.x % RL, slot = threadIdx.x / RL;
-    const int64_t b0 = (int64_t)blockIdx.x * SEG_B;
-    const int64_t b1 = (b0 + SEG_B < P) ? b0 + SEG_B : P;
-    const int run = (SEG_B + SL - 1) / SL;
-    const int64_t s0 = b0 + (int64_t)slot * run;
-    const int64_t s1 = (s0 + run < b1) ? s0 + run : b1;
-    const int first_row = keys[b0];
+    const int64_t b0 = (int64_t)blockIdx.x * B;
+    const int64_t b1 = (b0 + B < P) ? b0 + B : P;
+    const int cnt = (int)(b1 - b0);
+    if ((int)threadIdx.x < cnt) s_key[threadIdx.x] = keys[b0 + threadIdx.x];
+    // eight loads in flight per thread (clamped indices, no branch around
+    // the loads), then the LDS writes
+    const int nv = cnt * R;
+    for (int x0 = 0; x0 < nv; x0 += 256 * 8) {
+        float v[8];
+        int64_t ent[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int x = x0 + j * 256 + (int)threadIdx.x;
+            x = x < nv ? x : nv - 1;
+            const int e = x / R;
+            ent[j] = ids ? (int64_t)ids[b0 + e] : b0 + e;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int x = x0 + j * 256 + (int)threadIdx.x;
+            x = x < nv ? x : nv - 1;
+            v[j] = src[ent[j] * R + (x - (x / R) * R)];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int x = x0 + j * 256 + (int)threadIdx.x;
+            if (x < nv) s_val[x] = v[j];
+        }
+    }
+    __syncthreads();
+    const int run = (B + SL - 1) / SL;
+    const int s0 = slot * run;
+    const int s1 = (s0 + run < cnt) ? s0 + run : cnt;
+    const int first_row = s_key[0];
     float *hs = s_hsum;
     float *ts = s_hsum + SL * R;
     // per-slot sequential pass
     int cur = -1, head = -1;
     bool single = true;
     float acc = 0.0f, hsum = 0.0f;
-    for (int64_t e = s0; e < s1; ++e) {
-        const int row = keys[e];
-        const int64_t ent = ids ? (int64_t)ids[e] : e;
-        const float v = (r < R) ? src[ent * R + r] : 0.0f;
+    for (int e = s0; e < s1; ++e) {
+        const int row = s_key[e];
+        const float v = (r < R) ? s_val[e * R + r] : 0.0f;
         if (cur < 0) {
             cur = head = row;
         } else if (row != cur) {
@@ -612,13 +646,14 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         const int32_t *ids = p->split(n);
         const int32_t *keys = p->split(n) + p->npart[n];
         int64_t P = p->npart[n];
+        const int B = seg_block(L.R);
         for (int lvl = 0;; ++lvl) {
-            const int64_t nb = (P + SEG_B - 1) / SEG_B;
+            const int64_t nb = (P + B - 1) / B;
             const int last = nb == 1;
             float *nx = p->rt<float>(L.rt_seg[lvl & 1]);
             int32_t *nk = p->rt<int32_t>(L.rt_segk[lvl & 1]);
             hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, src, ids,
-                               keys, P, L.R, RL, out, nx, nk, last);
+                               keys, P, B, L.R, RL, out, nx, nk, last);
             HIPCHK(p, hipGetLastError());
             if (last) break;
             src = nx;
