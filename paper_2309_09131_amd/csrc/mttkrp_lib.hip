@@ -44,7 +44,7 @@ struct Layout {
     size_t off_xx, off_misc;           // persistent scalars
     size_t off_scratch, scratch_bytes, total;
     // runtime scratch (inside scratch)
-    size_t rt_carry, rt_partial, rt_G, rt_L, rt_Linv, rt_W, rt_gpart, rt_colsq, rt_lambda_tmp;
+    size_t rt_carry[2], rt_partial, rt_G, rt_L, rt_Linv, rt_W, rt_gpart, rt_colsq, rt_lambda_tmp;
     size_t rt_seg[2], rt_segk[2];
     // plan scratch (inside scratch)
     size_t ps_k0, ps_k1, ps_v0, ps_v1, ps_o0, ps_o1, ps_hist, ps_hscan, ps_sums, ps_err;
@@ -108,7 +108,8 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     // runtime scratch
     size_t r0 = 0;
     auto rtake = [&](size_t bytes) { size_t o = r0; r0 = align_up(r0 + bytes); return o; };
-    L->rt_carry = rtake((size_t)maxS * 2 * R * 4);
+    L->rt_carry[0] = rtake((size_t)maxS * 2 * R * 4);   // two: modes alternate
+    L->rt_carry[1] = rtake((size_t)maxS * 2 * R * 4);
     L->rt_partial = rtake((size_t)std::max<int64_t>(maxS, 4096) * 8);
     L->rt_G = rtake((size_t)N * R * R * 8);
     L->rt_L = rtake((size_t)R * R * 8);
@@ -160,6 +161,13 @@ struct mttkrp_plan_s {
     bool prof = false;
     std::vector<ProfEvent> events;
     std::vector<hipEvent_t> pool;
+    // second stream for the boundary-partial reduction, overlapped with the
+    // remap kernel; carry buffers alternate between consecutive passes
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_seg[2] = {nullptr, nullptr};
+    bool seg_pending[2] = {false, false};
+    bool aux_pending = false;
+    int carry_sel = 0;
 
     uint32_t *rec(int b) { return reinterpret_cast<uint32_t *>(ws + L.off_rec[b]); }
     int32_t *perm(int n) { return reinterpret_cast<int32_t *>(ws + L.off_perm[n]); }
@@ -591,7 +599,31 @@ static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
     return MTTKRP_OK;
 }
 
-// One MTTKRP-family pass over the current layout (mode == p->cur).
+static mttkrp_status ensure_aux(mttkrp_plan_t p)
+{
+    if (p->aux) return MTTKRP_OK;
+    HIPCHK(p, hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));   // default priority
+    HIPCHK(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->ev_seg[0], hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->ev_seg[1], hipEventDisableTiming));
+    return MTTKRP_OK;
+}
+
+// Make `s` wait for everything enqueued on the auxiliary stream so far.
+static mttkrp_status join_aux(mttkrp_plan_t p, hipStream_t s)
+{
+    if (!p->aux_pending) return MTTKRP_OK;
+    HIPCHK(p, hipEventRecord(p->ev_join, p->aux));
+    HIPCHK(p, hipStreamWaitEvent(s, p->ev_join, 0));
+    p->aux_pending = false;
+    p->seg_pending[0] = p->seg_pending[1] = false;
+    return MTTKRP_OK;
+}
+
+// One MTTKRP-family pass over the current layout (mode == p->cur).  The
+// reduction of rows split across shards runs on the auxiliary stream beside
+// the remap kernel; callers join it before `out` is read on `s`.
 static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_dtype fdt,
                               float *out, bool fuse, int kind, const double *gscale,
                               hipStream_t s)
@@ -623,7 +655,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.R = L.R;
     for (int w = 0; w < L.N; ++w) a.fac[w] = facs[w];
     a.out = out;
-    a.carry = p->rt<float>(L.rt_carry);
+    const int cs = p->carry_sel;
+    a.carry = p->rt<float>(L.rt_carry[cs]);
     a.gscale = gscale;
     a.partial = p->rt<double>(L.rt_partial);
     const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
@@ -635,12 +668,23 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         ev.b = take_event(p);
         if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
     }
+    const bool seg = kind != mk::KIND_LOSS && p->npart[n] > 0;
+    if (seg) {
+        mttkrp_status st = ensure_aux(p);
+        if (st != MTTKRP_OK) return st;
+        // the reduction that last read this carry buffer must be done
+        if (p->seg_pending[cs]) HIPCHK(p, hipStreamWaitEvent(s, p->ev_seg[cs], 0));
+        p->seg_pending[cs] = false;
+        p->carry_sel ^= 1;
+    }
     HIPCHK(p, launch_mttkrp_any(L.N, a, fdt == MTTKRP_BF16, c, kind, grid, s));
     if (prof) {
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);
     }
-    if (kind != mk::KIND_LOSS && p->npart[n] > 0) {
+    if (seg) {
+        HIPCHK(p, hipEventRecord(p->ev_fork, s));
+        HIPCHK(p, hipStreamWaitEvent(p->aux, p->ev_fork, 0));
         const int RL = std::min(256, next_pow2(L.R));
         const float *src = a.carry;
         const int32_t *ids = p->split(n);
@@ -652,8 +696,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
             const int last = nb == 1;
             float *nx = p->rt<float>(L.rt_seg[lvl & 1]);
             int32_t *nk = p->rt<int32_t>(L.rt_segk[lvl & 1]);
-            hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, src, ids,
-                               keys, P, B, L.R, RL, out, nx, nk, last);
+            hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, p->aux, src,
+                               ids, keys, P, B, L.R, RL, out, nx, nk, last);
             HIPCHK(p, hipGetLastError());
             if (last) break;
             src = nx;
@@ -661,6 +705,9 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
             ids = nullptr;
             P = 2 * nb;
         }
+        HIPCHK(p, hipEventRecord(p->ev_seg[cs], p->aux));
+        p->seg_pending[cs] = true;
+        p->aux_pending = true;
     }
     if (infuse) {
         p->buf ^= 1;
@@ -844,6 +891,12 @@ mttkrp_status mttkrp_plan_destroy(mttkrp_plan_t p)
         if (e.b) (void)hipEventDestroy(e.b);
     }
     for (auto e : p->pool) (void)hipEventDestroy(e);
+    if (p->aux) {
+        (void)hipStreamSynchronize(p->aux);
+        (void)hipStreamDestroy(p->aux);
+        for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_seg[0], p->ev_seg[1]})
+            if (e) (void)hipEventDestroy(e);
+    }
     delete p;
     return MTTKRP_OK;
 }
@@ -885,7 +938,9 @@ mttkrp_status mttkrp_mode(mttkrp_plan_t p, int mode, const void *const *d_factor
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     st = reach(p, mode, s);
     if (st != MTTKRP_OK) return st;
-    return run_pass(p, d_factors, fdt, d_out, fuse_remap != 0, mk::KIND_MTTKRP, nullptr, s);
+    st = run_pass(p, d_factors, fdt, d_out, fuse_remap != 0, mk::KIND_MTTKRP, nullptr, s);
+    if (st != MTTKRP_OK) return st;
+    return join_aux(p, s);
 }
 
 mttkrp_status mttkrp_all_modes(mttkrp_plan_t p, const void *const *d_factors, mttkrp_dtype fdt,
@@ -907,7 +962,7 @@ mttkrp_status mttkrp_all_modes(mttkrp_plan_t p, const void *const *d_factors, mt
         st = run_pass(p, d_factors, fdt, d_out[n], true, mk::KIND_MTTKRP, nullptr, s);
         if (st != MTTKRP_OK) return st;
     }
-    return MTTKRP_OK;
+    return join_aux(p, s);
 }
 
 mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp_dtype fdt,
@@ -941,7 +996,7 @@ mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp
             if (st != MTTKRP_OK) return st;
         }
     }
-    return MTTKRP_OK;
+    return join_aux(p, s);
 }
 
 mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
@@ -988,6 +1043,7 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
         st = run_pass(p, (const void *const *)d_factors, fdt, d_mbuf, true, mk::KIND_MTTKRP,
                       nullptr, s);
         if (st != MTTKRP_OK) return st;
+        if ((st = join_aux(p, s)) != MTTKRP_OK) return st;      // M_n complete on s
         hipLaunchKernelGGL(als::chol_inverse, dim3(1), dim3(256), 0, s, G, N, n, R,
                            p->rt<double>(L.rt_L), p->rt<double>(L.rt_Linv), p->rt<double>(L.rt_W),
                            p->ridge(), p->fail());
