@@ -9,7 +9,7 @@
 
 namespace als {
 
-constexpr int APPLY_BLOCKS = 512;   // blocks (and partial rows) of apply kernels
+constexpr int APPLY_BLOCKS = 2048;  // blocks (and partial rows) of apply kernels
 constexpr int GRAM_TILE = 16;
 
 template <typename FT>
@@ -22,30 +22,60 @@ __device__ __forceinline__ double ld<uint16_t>(const uint16_t *A, int64_t i)
     return (double)bf16_to_f32(A[i]);
 }
 
-// Partial Gram over a row range: grid = (gb, tiles, tiles), 16x16 threads.
+// Partial Gram over a row range: grid = (gb, tiles, tiles), 256 threads as
+// a 16 x 16 tile of G.  Rows are staged 64 at a time in LDS (coalesced,
+// clamped loads), then every thread accumulates its entry from LDS.
 // part[b][p][q] = sum_{i in chunk b} A[i][p] A[i][q].
 template <typename FT>
 __global__ __launch_bounds__(256) void gram_partial(const FT *__restrict__ A, int64_t I, int R,
                                                     int64_t chunk, double *__restrict__ part)
 {
-    const int p = blockIdx.y * GRAM_TILE + threadIdx.y;
-    const int q = blockIdx.z * GRAM_TILE + threadIdx.x;
+    __shared__ double sp[64][GRAM_TILE + 1], sq[64][GRAM_TILE + 1];
+    const int tx = threadIdx.x % GRAM_TILE, ty = threadIdx.x / GRAM_TILE;
+    const int p0 = blockIdx.y * GRAM_TILE, q0 = blockIdx.z * GRAM_TILE;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = (i0 + chunk < I) ? i0 + chunk : I;
     double acc = 0.0;
-    if (p < R && q < R)
-        for (int64_t i = i0; i < i1; ++i) acc += ld<FT>(A, i * R + p) * ld<FT>(A, i * R + q);
-    if (p < R && q < R) part[((int64_t)blockIdx.x * R + p) * R + q] = acc;
+    for (int64_t ib = i0; ib < i1; ib += 64) {
+        double vp[4], vq[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + k * 256;
+            const int row = e / GRAM_TILE, col = e % GRAM_TILE;
+            const int64_t i = ib + row;
+            const bool okr = i < i1;
+            const int64_t ic = okr ? i : i0;
+            const int pc = (p0 + col < R) ? p0 + col : R - 1;
+            const int qc = (q0 + col < R) ? q0 + col : R - 1;
+            const double a = ld<FT>(A, ic * R + pc), b = ld<FT>(A, ic * R + qc);
+            vp[k] = (okr && p0 + col < R) ? a : 0.0;
+            vq[k] = (okr && q0 + col < R) ? b : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + k * 256;
+            sp[e / GRAM_TILE][e % GRAM_TILE] = vp[k];
+            sq[e / GRAM_TILE][e % GRAM_TILE] = vq[k];
+        }
+        __syncthreads();
+#pragma unroll 16
+        for (int rr = 0; rr < 64; ++rr) acc += sp[rr][ty] * sq[rr][tx];
+        __syncthreads();
+    }
+    if (p0 + ty < R && q0 + tx < R) part[((int64_t)blockIdx.x * R + p0 + ty) * R + q0 + tx] = acc;
 }
 
-// G[p][q] = sum_b part[b][p][q] in block order.
-__global__ void gram_reduce(const double *__restrict__ part, int gb, int R, double *__restrict__ G)
+// G[t] = sum_b part[b][t]: one block per entry, strided partial sums then a
+// fixed tree (deterministic).
+__global__ __launch_bounds__(64) void gram_reduce(const double *__restrict__ part, int gb, int R,
+                                                 double *__restrict__ G)
 {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < R * R; t += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < gb; ++b) s += part[(int64_t)b * R * R + t];
-        G[t] = s;
-    }
+    const int t = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < gb; b += 64) v += part[(int64_t)b * R * R + t];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+    if (threadIdx.x == 0) G[t] = v;
 }
 
 // One block of 256 threads.  V = hadamard_{w != n} G_w; Cholesky (lower) in
@@ -147,7 +177,9 @@ __device__ __forceinline__ void st<uint16_t>(uint16_t *A, int64_t i, double x)
 
 // X = M W row by row (FP64).  pass 0: colsq[block][r] = sum of X(i,r)^2 over
 // the block's rows.  pass 1: A(i,r) = X(i,r) / lambda_r (lambda_r = 0: X).
-// Threads: rows-per-iteration RP = 256 / RT, RT = threads per row >= R.
+// Threads: RT per row (RT >= R, a power of two), RP = 256 / RT rows at a
+// time; the RP rows of M are staged in LDS with one coalesced load each,
+// and W sits in LDS when it fits (R <= 64).
 template <typename FT>
 __global__ __launch_bounds__(256) void als_apply(const float *__restrict__ M, int64_t I, int R,
                                                  int RT, const double *__restrict__ W,
@@ -156,22 +188,31 @@ __global__ __launch_bounds__(256) void als_apply(const float *__restrict__ M, in
                                                  FT *__restrict__ A)
 {
     __shared__ double red[256];
+    __shared__ double sW[64 * 64];
+    __shared__ float sM[256];                  // RP * R <= 256 because RT >= R
     const int r = threadIdx.x % RT, g = threadIdx.x / RT, RP = 256 / RT;
+    const bool wl = R <= 64;
+    if (wl)
+        for (int e = threadIdx.x; e < R * R; e += 256) sW[e] = W[e];
+    __syncthreads();
+    const double *Wp = wl ? sW : W;
+    const double lam = (pass == 1 && r < R) ? lambda[r] : 1.0;
     double acc = 0.0;
     const int64_t per = (I + gridDim.x - 1) / gridDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * per;
     const int64_t i1 = (i0 + per < I) ? i0 + per : I;
-    if (r < R) {
-        for (int64_t i = i0 + g; i < i1; i += RP) {
-            const float *m = M + i * R;
+    for (int64_t ib = i0; ib < i1; ib += RP) {
+        const int nrow = (int)((ib + RP < i1) ? RP : i1 - ib);
+        for (int e = threadIdx.x; e < nrow * R; e += 256) sM[e] = M[ib * R + e];
+        __syncthreads();
+        if (r < R && g < nrow) {
+            const float *m = sM + g * R;
             double x = 0.0;
-            for (int q = 0; q < R; ++q) x += (double)m[q] * W[q * R + r];
+            for (int q = 0; q < R; ++q) x += (double)m[q] * Wp[q * R + r];
             if (pass == 0) acc += x * x;
-            else {
-                const double lam = lambda[r];
-                st<FT>(A, i * R + r, lam > 0.0 ? x / lam : x);
-            }
+            else st<FT>(A, (ib + g) * R + r, lam > 0.0 ? x / lam : x);
         }
+        __syncthreads();
     }
     if (pass == 0) {
         red[threadIdx.x] = acc;
@@ -202,15 +243,14 @@ __device__ __forceinline__ double block_sum_strided(const double *__restrict__ p
     return r;
 }
 
-// lambda_r = sqrt(sum_b colsq[b][r]); one block of 256 threads.
+// lambda_r = sqrt(sum_b colsq[b][r]); one block of 256 threads per column.
 __global__ __launch_bounds__(256) void lambda_kernel(const double *__restrict__ colsq, int nb,
                                                      int R, double *__restrict__ lambda)
 {
     __shared__ double red[256];
-    for (int r = 0; r < R; ++r) {
-        const double s = block_sum_strided(colsq + r, nb, R, red);
-        if (threadIdx.x == 0) lambda[r] = sqrt(s);
-    }
+    const int r = blockIdx.x;
+    const double s = block_sum_strided(colsq + r, nb, R, red);
+    if (threadIdx.x == 0) lambda[r] = sqrt(s);
 }
 
 // inner[b][r] = sum over the block's rows of M(i,r) * A(i,r).

@@ -1013,18 +1013,20 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
     double *G = p->rt<double>(L.rt_G);
     double *gpart = p->rt<double>(L.rt_gpart);
     const int tiles = (R + als::GRAM_TILE - 1) / als::GRAM_TILE;
-    const int gb = std::max(1, GRAM_TARGET_BLOCKS / (tiles * tiles));
+    const int gbmax = std::max(1, GRAM_TARGET_BLOCKS / (tiles * tiles));
     auto gram = [&](int w) -> mttkrp_status {
         const int64_t I = L.dims[w];
+        // at least 256 rows per block
+        const int gb = (int)std::max<int64_t>(1, std::min<int64_t>(gbmax, (I + 255) / 256));
         const int64_t chunk = (I + gb - 1) / gb;
-        const dim3 grid(gb, tiles, tiles), blk(als::GRAM_TILE, als::GRAM_TILE);
+        const dim3 grid(gb, tiles, tiles), blk(256);
         if (bf)
             hipLaunchKernelGGL(als::gram_partial<uint16_t>, grid, blk, 0, s,
                                (const uint16_t *)d_factors[w], I, R, chunk, gpart);
         else
             hipLaunchKernelGGL(als::gram_partial<float>, grid, blk, 0, s,
                                (const float *)d_factors[w], I, R, chunk, gpart);
-        hipLaunchKernelGGL(als::gram_reduce, dim3(grid_for(R * R)), dim3(256), 0, s, gpart, gb, R,
+        hipLaunchKernelGGL(als::gram_reduce, dim3(R * R), dim3(64), 0, s, gpart, gb, R,
                            G + (int64_t)w * R * R);
         HIPCHK(p, hipGetLastError());
         return MTTKRP_OK;
@@ -1052,14 +1054,14 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
         if (bf) {
             hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
                                d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (uint16_t *)d_factors[n]);
-            hipLaunchKernelGGL(als::lambda_kernel, dim3(1), dim3(256), 0, s, colsq,
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, s, colsq,
                                als::APPLY_BLOCKS, R, d_lambda);
             hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
                                d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (uint16_t *)d_factors[n]);
         } else {
             hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
                                d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (float *)d_factors[n]);
-            hipLaunchKernelGGL(als::lambda_kernel, dim3(1), dim3(256), 0, s, colsq,
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, s, colsq,
                                als::APPLY_BLOCKS, R, d_lambda);
             hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
                                d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (float *)d_factors[n]);
