@@ -101,8 +101,7 @@ hipError_t launch_remap<NM>(const uint32_t *rin, uint32_t *rout, const int32_t *
     if (nnz <= 0) return hipSuccess;
     // one block per chunk of 256 * RT records (RT as in remap_kernel), the
     // grid rounded up to a multiple of the 8 XCDs
-    constexpr int RTC = (96 * 1024) / (256 * (4 * (NM + 1) + 4));
-    constexpr int RT = 16 < RTC ? 16 : RTC;
+    constexpr int RT = remap_rt<NM>();
     const int64_t nchunks = (nnz + 256 * RT - 1) / (256 * RT);
     unsigned grid = (unsigned)(((nchunks + 7) / 8) * 8);
     hipLaunchKernelGGL((remap_kernel<NM>), dim3(grid), dim3(256), 0, s, rin, rout, perm, nnz);

@@ -449,20 +449,33 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
 // leave in the same store instruction and the L2 combines them into one
 // write.  The result does not depend on the store order (every record has
 // its own destination).
+//
+// Records per thread (RT): 16, fewer when the LDS stage of 256 * RT records
+// plus their targets would exceed 96 KB.  The host sizes the grid with the
+// same function.
+template <int N>
+__host__ __device__ constexpr int remap_rt()
+{
+#ifdef MK_RT
+    constexpr int RT0 = MK_RT;
+#else
+    constexpr int RT0 = 16;
+#endif
+#ifdef MK_LDSKB
+    constexpr int RTC = (MK_LDSKB * 1024) / (256 * (4 * (N + 1) + 4));
+#else
+    constexpr int RTC = (96 * 1024) / (256 * (4 * (N + 1) + 4));
+#endif
+    return RT0 < RTC ? RT0 : RTC;
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__ rin,
                                                     uint32_t *__restrict__ rout,
                                                     const int32_t *__restrict__ perm,
                                                     int64_t nnz)
 {
-#ifdef MK_RT
-    constexpr int RT0 = MK_RT;
-#else
-    constexpr int RT0 = 16;               // records per thread
-#endif
-    // keep the LDS stage within 96 KB for wide records
-    constexpr int RTC = (96 * 1024) / (256 * (4 * (N + 1) + 4));
-    constexpr int RT = RT0 < RTC ? RT0 : RTC;
+    constexpr int RT = remap_rt<N>();
     constexpr int RB = 256 * RT;
 #ifdef MK_NB
     constexpr int NB = MK_NB;
