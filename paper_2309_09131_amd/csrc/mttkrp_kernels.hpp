@@ -144,7 +144,9 @@ __device__ __forceinline__ bool lane_active(int sub, int R)
     else return sub * V < R;
 }
 
-// The N-1 input modes of output mode n, in increasing order (uniform).
+// The N-1 input modes of output mode n in the layout's key order
+// n-1, n-2, ..., n+1 (cyclic, uniform).  Input 0 is the layout's second
+// key: inside an output row the nonzeros are sorted by it.
 template <int N>
 struct Inputs {
     const void *fac[N > 1 ? N - 1 : 1];
@@ -153,24 +155,25 @@ struct Inputs {
     {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) {
-            const int w = k + (k >= n ? 1 : 0);
+            const int w = (n + N - 1 - k) % N;
             mode[k] = w;
             fac[k] = a.fac[w];
         }
     }
 };
 
-// Hadamard product of the input factor rows of one nonzero.  Every load is
-// unconditional (the caller passes an in-range record and lane), so the
-// compiler can keep all gathers of an unrolled group in flight at once.
-template <int N, typename FT, int V, bool STRIDED>
+// Product of the factor rows of inputs K0..N-2 of one nonzero (ones when
+// there are none).  Every load is unconditional (the caller passes an
+// in-range record and lane), so the compiler can keep all gathers of an
+// unrolled group in flight at once.
+template <int N, typename FT, int V, bool STRIDED, int K0>
 __device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<N> &rc, int R,
                                             int sub, float (&pr)[V])
 {
 #pragma unroll
     for (int j = 0; j < V; ++j) pr[j] = 1.0f;
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) {
+    for (int k = K0; k < N - 1; ++k) {
         float x[V];
         Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)rec_coord<N>(rc, in.mode[k]), R, sub, x);
 #pragma unroll
@@ -254,6 +257,18 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
 
     const Inputs<N> in(a, n);
     const int fsub = ract ? sub : 0;             // in-range lane for loads
+    // Row reuse for input 0 (FP32 factors).  Inside an output row the
+    // nonzeros are sorted by the input-0 coordinate, so consecutive nonzeros
+    // of a slot often need the same input-0 row (about 70% of them on
+    // Zipf-skewed tensors).  That row is then loaded only when the
+    // coordinate changes and the slot uses the row it loaded last; the
+    // products are the same.  (With BF16 factors the extra registers cost
+    // more occupancy than the skipped loads save.)
+    constexpr bool REUSE = sizeof(FT) == 4 && N > 2;
+    float xp[V];
+    int pc0 = -1;
+#pragma unroll
+    for (int j = 0; j < V; ++j) xp[j] = 0.0f;
     // Records are loaded once per lane group, not once per lane: lane `sub`
     // of a slot loads records sub, sub + LANES, ... of the slot's next U
     // nonzeros (RPL per lane), and the words are then broadcast inside the
@@ -288,9 +303,44 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
         }
         float pr[U][V];
         float mm[U];
+        if constexpr (REUSE) {
+            int c0[U];
+            bool need[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c0[u] = (int)rec_coord<N>(rc[u], in.mode[0]);
+                need[u] = ok[u] && c0[u] != (u == 0 ? pc0 : c0[u - 1]);
+            }
+            float x0[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) x0[u][j] = 0.0f;
+                if (need[u]) Fetch<FT, V, STRIDED>::get(in.fac[0], (int64_t)c0[u], R, fsub, x0[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) pc0 = c0[u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                row_product<N, FT, V, STRIDED, 1>(in, rc[u], R, fsub, pr[u]);
+                // opaque copy of the flag: keeps the compiler from folding
+                // the selection into the conditional load, which would make
+                // each load wait for the one before it
+                int sel = need[u] ? 1 : 0;
+                asm volatile("" : "+v"(sel));
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    xp[j] = sel ? x0[u][j] : xp[j];
+                    pr[u][j] = xp[j] * pr[u][j];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) row_product<N, FT, V, STRIDED, 0>(in, rc[u], R, fsub, pr[u]);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            row_product<N, FT, V, STRIDED>(in, rc[u], R, fsub, pr[u]);
             mm[u] = 0.0f;
             if constexpr (RESID) {
                 float xn[V];
