@@ -257,18 +257,30 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
 
     const Inputs<N> in(a, n);
     const int fsub = ract ? sub : 0;             // in-range lane for loads
-    // Row reuse for input 0 (FP32 factors).  Inside an output row the
-    // nonzeros are sorted by the input-0 coordinate, so consecutive nonzeros
-    // of a slot often need the same input-0 row (about 70% of them on
-    // Zipf-skewed tensors).  That row is then loaded only when the
+    // Row reuse for the first NR inputs (FP32 factors).  Inside an output
+    // row the nonzeros are sorted by the input-0 coordinate, then input 1,
+    // so consecutive nonzeros of a slot often need the same input-0 row
+    // (70-99% of them on Zipf-skewed tensors) and, with five or more modes,
+    // the same input-1 row (30-75%).  Such a row is loaded only when its
     // coordinate changes and the slot uses the row it loaded last; the
-    // products are the same.  (With BF16 factors the extra registers cost
-    // more occupancy than the skipped loads save.)
-    constexpr bool REUSE = sizeof(FT) == 4 && N > 2;
-    float xp[V];
-    int pc0 = -1;
+    // products are the same.  NR = 1, or 2 from five modes on (measured;
+    // with four modes the registers of a second input cost more occupancy
+    // than the loads save, and with BF16 factors even the first does).
+#ifdef MK_NR
+    constexpr int NR0 = MK_NR;
+#else
+    constexpr int NR0 = N >= 5 ? 2 : 1;
+#endif
+    constexpr int NR = (sizeof(FT) == 4 && N > 2) ? (N - 2 < NR0 ? N - 2 : NR0) : 0;
+    constexpr bool REUSE = NR > 0;
+    float xp[NR > 0 ? NR : 1][V];
+    int pc[NR > 0 ? NR : 1];
 #pragma unroll
-    for (int j = 0; j < V; ++j) xp[j] = 0.0f;
+    for (int k = 0; k < NR; ++k) {
+        pc[k] = -1;
+#pragma unroll
+        for (int j = 0; j < V; ++j) xp[k][j] = 0.0f;
+    }
     // Records are loaded once per lane group, not once per lane: lane `sub`
     // of a slot loads records sub, sub + LANES, ... of the slot's next U
     // nonzeros (RPL per lane), and the words are then broadcast inside the
@@ -304,35 +316,45 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
         float pr[U][V];
         float mm[U];
         if constexpr (REUSE) {
-            int c0[U];
-            bool need[U];
+            int cc[NR][U];
+            bool need[NR][U];
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    cc[k][u] = (int)rec_coord<N>(rc[u], in.mode[k]);
+                    need[k][u] = ok[u] && cc[k][u] != (u == 0 ? pc[k] : cc[k][u - 1]);
+                }
+            float xr[NR][U][V];
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) xr[k][u][j] = 0.0f;
+                    if (need[k][u])
+                        Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)cc[k][u], R, fsub, xr[k][u]);
+                }
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) pc[k] = cc[k][u];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                c0[u] = (int)rec_coord<N>(rc[u], in.mode[0]);
-                need[u] = ok[u] && c0[u] != (u == 0 ? pc0 : c0[u - 1]);
-            }
-            float x0[U][V];
+                row_product<N, FT, V, STRIDED, NR>(in, rc[u], R, fsub, pr[u]);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+                for (int k = NR - 1; k >= 0; --k) {
+                    // opaque copy of the flag: keeps the compiler from
+                    // folding the selection into the conditional load, which
+                    // would make each load wait for the one before it
+                    int sel = need[k][u] ? 1 : 0;
+                    asm volatile("" : "+v"(sel));
 #pragma unroll
-                for (int j = 0; j < V; ++j) x0[u][j] = 0.0f;
-                if (need[u]) Fetch<FT, V, STRIDED>::get(in.fac[0], (int64_t)c0[u], R, fsub, x0[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) pc0 = c0[u];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                row_product<N, FT, V, STRIDED, 1>(in, rc[u], R, fsub, pr[u]);
-                // opaque copy of the flag: keeps the compiler from folding
-                // the selection into the conditional load, which would make
-                // each load wait for the one before it
-                int sel = need[u] ? 1 : 0;
-                asm volatile("" : "+v"(sel));
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    xp[j] = sel ? x0[u][j] : xp[j];
-                    pr[u][j] = xp[j] * pr[u][j];
+                    for (int j = 0; j < V; ++j) {
+                        xp[k][j] = sel ? xr[k][u][j] : xp[k][j];
+                        pr[u][j] = xp[k][j] * pr[u][j];
+                    }
                 }
             }
         } else {
