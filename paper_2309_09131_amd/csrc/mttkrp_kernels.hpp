@@ -576,8 +576,15 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
         for (int k = 0; k < RT; ++k) {
             const int64_t i = base + k * 256 + t;
             const bool ok = i < nnz;
-            r[k] = load_rec<N>(rin, ok ? i : 0);
-            d[k] = ok ? perm[i] : -1;
+            // Read-once streams are loaded non-temporal, so they do not
+            // evict the partly written destination lines that wait in L2 for
+            // their other records.  Records only when one 16-byte load (or
+            // two) covers them: a record read by a 16-byte and a 4-byte load
+            // touches its lines twice, and a streamed line can be gone before
+            // the second load (measured slower with 4 and 5 modes).
+            if constexpr ((N + 1) % 4 == 0) r[k] = load_rec_nt<N>(rin, ok ? i : 0);
+            else r[k] = load_rec<N>(rin, ok ? i : 0);
+            d[k] = ok ? __builtin_nontemporal_load(perm + i) : -1;
         }
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
