@@ -336,6 +336,25 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
     bwd_b = sum(nnz * (2 * E + N * R * 4) + dims[k] * R * 4 for k in range(N))
     value = (fwd_b + bwd_b) / (ms * 1e-3) / 1e9
     log(f"loss fwd+bwd {ms:.3f} ms (fwd {fwd_ms:.3f} ms)")
+    # per-kernel means from the library's HIP events (same steps again)
+    plan.profile(True)
+    step()
+    torch.cuda.synchronize()
+    for k in (_abi.PROF_RESID, _abi.PROF_LOSS, _abi.PROF_REMAP):
+        plan.profile_read(k)
+    timer(step, args.steps, 0)
+    resid = [plan.profile_read(_abi.PROF_RESID, n) for n in range(N)]
+    lossk = plan.profile_read(_abi.PROF_LOSS)
+    remk = plan.profile_read(_abi.PROF_REMAP)
+    plan.profile(False)
+    r_ms = sum(m for m, _ in resid)
+    r_launch = sum(c for _, c in resid)
+    r_bytes = sum((nnz * (E + N * R * 4) + dims[n] * R * 4) * resid[n][1] for n in range(N))
+    r_gbs = r_bytes / (r_ms * 1e-3) / 1e9
+    l_gbs = nnz * (E + N * R * 4) * lossk[1] / (lossk[0] * 1e-3) / 1e9
+    log(f"residual MTTKRP kernel {r_ms / r_launch:.4f} ms/launch ({r_gbs:.0f} GB/s), "
+        f"loss kernel {lossk[0] / lossk[1]:.4f} ms ({l_gbs:.0f} GB/s), remap "
+        f"{remk[0] / max(remk[1], 1):.4f} ms")
 
     # checks on a 10K-nonzero subsample (first in generation order)
     S = 10_000
@@ -399,7 +418,17 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
         "config": {"workload": w.name, "dims": list(dims), "nnz": nnz, "rank": R,
                    "step": "sampled CP loss forward + autograd backward to all factors",
                    "plan_ms": round(plan_ms, 1)},
-        "roofline": None, "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
+        "roofline": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "mk::mttkrp_kernel residual form (loss gradient, per mode)",
+                     "kernel_ms_per_launch": round(r_ms / r_launch, 4),
+                     "alg_bytes_per_launch": int(r_bytes / r_launch),
+                     "note": "algorithmic bytes: record + N gathered factor rows per nonzero "
+                             "+ the gradient rows; most gathers hit L2/MALL"},
+        "loss_kernel": {"ms_per_launch": round(lossk[0] / lossk[1], 4),
+                        "alg_bytes_per_launch": int(nnz * (E + N * R * 4)),
+                        "achieved_GBs": round(l_gbs, 1)},
+        "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
         "checks": checks,
     }
 

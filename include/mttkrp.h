@@ -199,13 +199,17 @@ enum {
 mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *value);
 
 /* Kernel timing with HIP events on the launch stream: when enabled, every
- * launch of the per-mode MTTKRP kernel and of the remap kernel is bracketed
- * by events.  mttkrp_profile_read synchronises and returns the summed
- * milliseconds and launch count of `kernel` (MTTKRP_PROF_MTTKRP or
- * MTTKRP_PROF_REMAP) for `mode` (-1: all modes; for the remap kernel, the
- * mode it remaps from) since the last read, and resets those events. */
+ * launch of the per-mode MTTKRP kernel, the remap kernel, the residual
+ * (loss-gradient) MTTKRP kernel and the loss kernel is bracketed by events.
+ * mttkrp_profile_read synchronises and returns the summed milliseconds and
+ * launch count of `kernel` (one of the MTTKRP_PROF_* ids) for `mode` (-1:
+ * all modes; for the remap kernel, the mode it remaps from; the loss kernel
+ * runs on the layout of its mode) since the last read, and resets those
+ * events. */
 #define MTTKRP_PROF_MTTKRP 0
 #define MTTKRP_PROF_REMAP 1
+#define MTTKRP_PROF_RESID 2
+#define MTTKRP_PROF_LOSS 3
 mttkrp_status mttkrp_profile(mttkrp_plan_t p, int enable);
 mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int kernel, int mode, double *ms,
                                   int64_t *launches);

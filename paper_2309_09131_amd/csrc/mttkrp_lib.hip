@@ -661,8 +661,11 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.partial = p->rt<double>(L.rt_partial);
     const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
     const unsigned grid = (unsigned)((p->nshards[n] + 3) / 4);
-    ProfEvent ev{nullptr, nullptr, n, 0};
-    const bool prof = p->prof && kind == mk::KIND_MTTKRP;
+    const int pk = kind == mk::KIND_MTTKRP  ? MTTKRP_PROF_MTTKRP
+                   : kind == mk::KIND_RESID ? MTTKRP_PROF_RESID
+                                            : MTTKRP_PROF_LOSS;
+    ProfEvent ev{nullptr, nullptr, n, pk};
+    const bool prof = p->prof;
     if (prof) {
         ev.a = take_event(p);
         ev.b = take_event(p);
@@ -1148,7 +1151,7 @@ mttkrp_status mttkrp_profile_read(mttkrp_plan_t p, int kernel, int mode, double 
                                   int64_t *launches)
 {
     if (!p || !ms || !launches) return fail(p, MTTKRP_EINVAL, "NULL argument");
-    if (kernel != MTTKRP_PROF_MTTKRP && kernel != MTTKRP_PROF_REMAP)
+    if (kernel < MTTKRP_PROF_MTTKRP || kernel > MTTKRP_PROF_LOSS)
         return fail(p, MTTKRP_EINVAL, "bad kernel id");
     double tot = 0.0;
     int64_t cnt = 0;

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from gpu_common import (BF16_TOL, FP32_TOL, _abi, bf16_round, check_close,
-                        dev, oracle, say, to_dev)
+                        dev, make_plan, oracle, say, to_dev)
 from paper_2309_09131_amd import synthetic as syn
 from paper_2309_09131_amd.api import Plan, cp_loss
 
@@ -182,3 +182,34 @@ def test_cp_als_gpu_converges_on_planted_tensor():
     for _ in range(200):
         lam, fit = p.cp_als_sweep(facs)
     assert fit.item() > 1 - 1e-4, fit.item()
+
+
+def test_profile_events_count_every_kernel_launch():
+    """mttkrp_profile brackets each MTTKRP, remap, residual-MTTKRP and loss
+    launch with HIP events; reads return one launch per mode per pass and
+    reset what they returned."""
+    dims, R = (60, 50, 40, 30), 16
+    t = syn.random_tensor(dims, 4000, R, 77, zipf_s=1.1)
+    p, facs = make_plan(t, g=64)
+    N = len(dims)
+    p.profile(True)
+    p.mttkrp_all_modes(facs)
+    p.cp_loss_grad(facs)
+    torch.cuda.synchronize()
+    for n in range(N):
+        ms, c = p.profile_read(_abi.PROF_MTTKRP, n)
+        assert c == 1 and ms > 0, (n, ms, c)
+        ms, c = p.profile_read(_abi.PROF_RESID, n)
+        assert c == 1 and ms > 0, (n, ms, c)
+    ms, c = p.profile_read(_abi.PROF_LOSS)
+    assert c == 1 and ms > 0
+    ms, c = p.profile_read(_abi.PROF_REMAP)
+    assert c == 2 * N and ms > 0          # one remap per pass of both sweeps
+    for k in (_abi.PROF_MTTKRP, _abi.PROF_RESID, _abi.PROF_LOSS, _abi.PROF_REMAP):
+        assert p.profile_read(k) == (0.0, 0)
+    p.profile(False)
+    p.mttkrp_all_modes(facs)
+    torch.cuda.synchronize()
+    assert p.profile_read(_abi.PROF_MTTKRP) == (0.0, 0)
+    with pytest.raises(_abi.MttkrpError):
+        p.profile_read(4)
