@@ -168,6 +168,22 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors,
                            mttkrp_dtype fdt, float *d_mbuf, double *d_lambda,
                            double *d_fit, void *stream);
 
+/*
+ * CP-ALS to convergence (Alg. "cp-als" with its loop): sweeps as in
+ * cp_als_sweep until two consecutive fits differ by less than tol, or
+ * max_sweeps sweeps.  The Gram matrices are computed once at the start and
+ * then kept current (each mode update refreshes its own), not recomputed
+ * every sweep; the results equal max_sweeps calls of cp_als_sweep.
+ * Synchronises `stream` after every sweep to read the fit.
+ *   max_sweeps   >= 1;  tol >= 0 (0: run max_sweeps sweeps).
+ *   d_fit_trace  device double[max_sweeps] or NULL: the fit after each sweep.
+ *   sweeps, fit  host out (nullable): sweeps run and the last fit.
+ * Other arguments as in cp_als_sweep.
+ */
+mttkrp_status cp_als(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                     float *d_mbuf, double *d_lambda, int max_sweeps, double tol,
+                     double *d_fit_trace, int *sweeps, double *fit, void *stream);
+
 /* Device-side plan arrays, copied into caller memory (for parity tests). */
 enum {
     MTTKRP_Q_LAYOUT = 0,   /* current element buffer: nnz x (N int32 + f32) */

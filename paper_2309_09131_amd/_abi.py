@@ -26,7 +26,7 @@ INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2
 INFO_NSPLIT, INFO_G, INFO_M, INFO_RIDGE = 4, 5, 6, 7
 
 SYMBOLS = ["mttkrp_plan_workspace", "mttkrp_plan", "mttkrp_mode",
-           "mttkrp_all_modes", "remap", "cp_loss_grad", "cp_als_sweep",
+           "mttkrp_all_modes", "remap", "cp_loss_grad", "cp_als_sweep", "cp_als",
            "mttkrp_plan_query", "mttkrp_plan_info", "mttkrp_profile",
            "mttkrp_profile_read", "mttkrp_plan_destroy", "mttkrp_status_str",
            "mttkrp_last_error"]
@@ -65,6 +65,8 @@ def load():
         "remap": [_vp, _int, _vp],
         "cp_loss_grad": [_vp, _vp, _int, _vp, _vp, _vp, _vp],
         "cp_als_sweep": [_vp, _vp, _int, _vp, _vp, _vp, _vp],
+        "cp_als": [_vp, _vp, _int, _vp, _vp, _int, ctypes.c_double, _vp,
+                   ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _vp],
         "mttkrp_plan_query": [_vp, _int, _int, _vp, ctypes.c_size_t, _vp],
         "mttkrp_plan_info": [_vp, _int, _int, ctypes.POINTER(_i64)],
         "mttkrp_profile": [_vp, _int],
@@ -155,6 +157,17 @@ def cp_als_sweep(plan, d_factors, fdt, d_mbuf, d_lambda, d_fit, stream=0):
     lib = load()
     _check(lib.cp_als_sweep(plan, _ptrs(d_factors), fdt, d_mbuf, d_lambda,
                             d_fit or None, stream or None), plan)
+
+
+def cp_als(plan, d_factors, fdt, d_mbuf, d_lambda, max_sweeps, tol, d_fit_trace=0, stream=0):
+    """Returns (sweeps run, last fit)."""
+    lib = load()
+    sweeps = _int(0)
+    fit = ctypes.c_double(0.0)
+    _check(lib.cp_als(plan, _ptrs(d_factors), fdt, d_mbuf, d_lambda, max_sweeps, tol,
+                      d_fit_trace or None, ctypes.byref(sweeps), ctypes.byref(fit),
+                      stream or None), plan)
+    return sweeps.value, fit.value
 
 
 def mttkrp_plan_query(plan, what, mode, dst, nbytes, stream=0):

@@ -2,8 +2,8 @@
 
 PyTorch supplies device memory and the stream; every step runs in the HIP
 library.  Names follow the C entry points (mttkrp_mode, mttkrp_all_modes,
-remap, cp_loss_grad, cp_als_sweep); `Plan` bundles the workspace tensor and
-the plan handle, `CpLoss` exposes the sampled CP loss to autograd.
+remap, cp_loss_grad, cp_als_sweep, cp_als); `Plan` bundles the workspace
+tensor and the plan handle, `CpLoss` exposes the sampled CP loss to autograd.
 """
 from __future__ import annotations
 
@@ -136,6 +136,21 @@ class Plan:
         _abi.cp_als_sweep(self.handle, [_ptr(f) for f in factors], _fdt(factors),
                           _ptr(mbuf), _ptr(lam), _ptr(fit), _stream())
         return lam, fit
+
+    def cp_als(self, factors, max_sweeps, tol=0.0, mbuf=None, lam=None, trace=True):
+        """CP-ALS until two consecutive fits differ by less than `tol` (or
+        `max_sweeps` sweeps); `factors` are updated in place.  Returns
+        (lambda, fits) with fits the FP64 fit after every sweep run."""
+        if mbuf is None:
+            mbuf = torch.empty((max(self.dims), self.rank), dtype=torch.float32,
+                               device=self.device)
+        if lam is None:
+            lam = torch.empty(self.rank, dtype=torch.float64, device=self.device)
+        tr = torch.empty(max_sweeps, dtype=torch.float64, device=self.device) if trace else None
+        k, fit = _abi.cp_als(self.handle, [_ptr(f) for f in factors], _fdt(factors),
+                             _ptr(mbuf), _ptr(lam), int(max_sweeps), float(tol), _ptr(tr),
+                             _stream())
+        return lam, (tr[:k] if trace else torch.tensor([fit], dtype=torch.float64))
 
     def profile(self, enable=True):
         _abi.mttkrp_profile(self.handle, enable)

@@ -326,6 +326,12 @@ __global__ __launch_bounds__(256) void sumsq_partial(const uint32_t *__restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Clear n int32 counters (a kernel rather than a memset: safe to capture).
+__global__ void zero_i32(int32_t *__restrict__ p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // out[0] = sum_b part[b] (one block of 256 threads, fixed order).
 __global__ __launch_bounds__(256) void sum_kernel(const double *__restrict__ part, int64_t nb,
                                                   double *__restrict__ out)

@@ -179,6 +179,7 @@ struct mttkrp_plan_s {
     double *xx() { return reinterpret_cast<double *>(ws + L.off_xx); }
     int32_t *ridge() { return reinterpret_cast<int32_t *>(ws + L.off_misc); }
     int32_t *fail() { return reinterpret_cast<int32_t *>(ws + L.off_misc) + 1; }
+    double *fit_slot() { return reinterpret_cast<double *>(ws + L.off_misc) + 1; }
     template <typename T> T *rt(size_t o) { return reinterpret_cast<T *>(ws + L.off_scratch + o); }
 };
 
@@ -1002,14 +1003,14 @@ mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp
     return join_aux(p, s);
 }
 
-mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
-                           float *d_mbuf, double *d_lambda, double *d_fit, void *stream)
+// One Gauss-Seidel sweep.  grams_valid: the Gram matrices of every mode are
+// those of the current stored factors (the previous sweep of the same
+// driver call left them so), and are not recomputed.
+static mttkrp_status als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                               float *d_mbuf, double *d_lambda, double *d_fit, bool grams_valid,
+                               hipStream_t s)
 {
-    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
-    mttkrp_status st = check_factors(p, (const void *const *)d_factors, 0, -1, fdt);
-    if (st != MTTKRP_OK) return st;
-    if (!d_mbuf || !d_lambda) return fail(p, MTTKRP_EINVAL, "mbuf/lambda is NULL");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mttkrp_status st;
     const Layout &L = p->L;
     const int N = L.N, R = L.R;
     const bool bf = fdt == MTTKRP_BF16;
@@ -1034,14 +1035,14 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
         HIPCHK(p, hipGetLastError());
         return MTTKRP_OK;
     };
-    HIPCHK(p, hipMemsetAsync(p->ridge(), 0, 8, s));
     const uint32_t saved = p->L.flags;
     p->L.flags &= ~MTTKRP_NO_IMPLICIT_REMAP;
     st = reach(p, 0, s);
     p->L.flags = saved;
     if (st != MTTKRP_OK) return st;
-    for (int w = 0; w < N; ++w)
-        if ((st = gram(w)) != MTTKRP_OK) return st;
+    if (!grams_valid)
+        for (int w = 0; w < N; ++w)
+            if ((st = gram(w)) != MTTKRP_OK) return st;
     const int RT = std::min(256, next_pow2(R));
     double *colsq = p->rt<double>(L.rt_colsq);
     for (int n = 0; n < N; ++n) {
@@ -1085,6 +1086,55 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
                            N, d_lambda, R, p->xx(), d_fit);
         HIPCHK(p, hipGetLastError());
     }
+    return MTTKRP_OK;
+}
+
+static mttkrp_status als_args(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                              float *d_mbuf, double *d_lambda)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    mttkrp_status st = check_factors(p, (const void *const *)d_factors, 0, -1, fdt);
+    if (st != MTTKRP_OK) return st;
+    if (!d_mbuf || !d_lambda) return fail(p, MTTKRP_EINVAL, "mbuf/lambda is NULL");
+    return MTTKRP_OK;
+}
+
+mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                           float *d_mbuf, double *d_lambda, double *d_fit, void *stream)
+{
+    mttkrp_status st = als_args(p, d_factors, fdt, d_mbuf, d_lambda);
+    if (st != MTTKRP_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(als::zero_i32, dim3(1), dim3(64), 0, s, p->ridge(), 2);
+    HIPCHK(p, hipGetLastError());
+    return als_sweep(p, d_factors, fdt, d_mbuf, d_lambda, d_fit, false, s);
+}
+
+mttkrp_status cp_als(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt, float *d_mbuf,
+                     double *d_lambda, int max_sweeps, double tol, double *d_fit_trace,
+                     int *sweeps, double *fit, void *stream)
+{
+    mttkrp_status st = als_args(p, d_factors, fdt, d_mbuf, d_lambda);
+    if (st != MTTKRP_OK) return st;
+    if (max_sweeps < 1) return fail(p, MTTKRP_EINVAL, "max_sweeps must be >= 1");
+    if (!(tol >= 0.0)) return fail(p, MTTKRP_EINVAL, "tol must be >= 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(als::zero_i32, dim3(1), dim3(64), 0, s, p->ridge(), 2);
+    HIPCHK(p, hipGetLastError());
+    double prev = 0.0, cur = 0.0;
+    int k = 0;
+    while (k < max_sweeps) {
+        double *slot = d_fit_trace ? d_fit_trace + k : p->fit_slot();
+        st = als_sweep(p, d_factors, fdt, d_mbuf, d_lambda, slot, k > 0, s);
+        if (st != MTTKRP_OK) return st;
+        HIPCHK(p, hipMemcpyAsync(&cur, slot, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        ++k;
+        if (k > 1 && std::fabs(cur - prev) < tol) break;
+        prev = cur;
+    }
+    if (sweeps) *sweeps = k;
+    if (fit) *fit = cur;
     return MTTKRP_OK;
 }
 

@@ -72,6 +72,7 @@ def test_calls_on_null_plan_are_einval(lib):
                      (lib.remap, (None, 0, None)),
                      (lib.cp_loss_grad, (None, None, 0, None, None, None, None)),
                      (lib.cp_als_sweep, (None, None, 0, None, None, None, None)),
+                     (lib.cp_als, (None, None, 0, None, None, 1, 0.0, None, None, None, None)),
                      (lib.mttkrp_plan_destroy, (None,))]:
         assert fn(*args) == _abi.EINVAL
     assert lib.mttkrp_status_str(_abi.ESTATE).decode().startswith("tensor")

@@ -213,3 +213,79 @@ def test_profile_events_count_every_kernel_launch():
     assert p.profile_read(_abi.PROF_MTTKRP) == (0.0, 0)
     with pytest.raises(_abi.MttkrpError):
         p.profile_read(4)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("case", ALS_CASES[:3])
+def test_cp_als_driver_equals_repeated_sweeps(case, dtype):
+    """cp_als keeps the Gram matrices across sweeps instead of recomputing
+    them; the Grams it keeps are those of the stored factors, so k sweeps of
+    the driver are bit-identical to k calls of cp_als_sweep."""
+    dims, nnz, R, seed, g = case
+    say("als driver case", case, dtype)
+    t = syn.random_tensor(dims, nnz, R, seed)
+    idx, vals, f0 = to_dev(t, dtype)
+    pa = Plan(idx, vals, dims, R, g=g)
+    pb = Plan(idx, vals, dims, R, g=g)
+    fa = [f.clone() for f in f0]
+    fb = [f.clone() for f in f0]
+    lam_a, fits = pa.cp_als(fa, max_sweeps=4, tol=0.0)
+    assert fits.numel() == 4
+    sweep_fits = []
+    for _ in range(4):
+        lam_b, fit_b = pb.cp_als_sweep(fb)
+        sweep_fits.append(fit_b.item())
+    torch.cuda.synchronize()
+    for a, b in zip(fa, fb):
+        assert torch.equal(a, b)
+    assert torch.equal(lam_a, lam_b)
+    assert fits.cpu().tolist() == sweep_fits
+    # a tolerance above any fit change stops after two sweeps
+    lam_c, fits_c = pa.cp_als([f.clone() for f in f0], max_sweeps=10, tol=2.0)
+    assert fits_c.numel() == 2
+
+
+def _dense_planted(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    true = [rng.standard_normal((d, R)) for d in dims]
+    idx = np.array(np.unravel_index(np.arange(int(np.prod(dims))), dims)).astype(np.int32)
+    m = np.zeros(idx.shape[1])
+    for r in range(R):
+        term = np.ones(idx.shape[1])
+        for n in range(len(dims)):
+            term *= true[n][idx[n], r]
+        m += term
+    perm = rng.permutation(idx.shape[1])
+    return idx[:, perm], m[perm].astype(np.float32), true
+
+
+@pytest.mark.parametrize("dims,R,seed", [((30, 30, 30), 8, 1), ((20, 20, 20, 20), 8, 3)])
+def test_cp_als_recovers_planted_dense_tensor(dims, R, seed):
+    """A fully stored rank-R tensor: the driver converges to fit ~1 and the
+    factor columns match the planted ones up to order and scale; the FP64
+    oracle, looped from the same start, converges too."""
+    idx, vals, true = _dense_planted(dims, R, seed)
+    rng = np.random.default_rng(seed + 7)
+    init = [rng.standard_normal((d, R)) for d in dims]
+    d = dev()
+    p = Plan(torch.from_numpy(idx).to(d), torch.from_numpy(vals).to(d), dims, R, g=256)
+    facs = [torch.from_numpy(f.astype(np.float32)).to(d) for f in init]
+    lam, fits = p.cp_als(facs, max_sweeps=400, tol=1e-10)
+    fits = fits.cpu().numpy()
+    say("  sweeps", len(fits), "fit", fits[-1])
+    assert fits[-1] > 1 - 1e-5, fits[-5:]
+    assert len(fits) < 400
+    for n in range(len(dims)):
+        a = facs[n].cpu().numpy().astype(np.float64)
+        a /= np.linalg.norm(a, axis=0)
+        b = true[n] / np.linalg.norm(true[n], axis=0)
+        cong = np.abs(a.T @ b).max(axis=0)          # best match of each planted column
+        assert cong.min() > 0.9999, (n, cong.min())
+    F = init
+    ofits = []
+    for _ in range(400):
+        F, _, ofit, _, _ = oracle.cp_als_sweep(dims, idx, vals, F)
+        ofits.append(ofit)
+        if len(ofits) > 1 and abs(ofits[-1] - ofits[-2]) < 1e-10:
+            break
+    assert ofits[-1] > 1 - 1e-5
