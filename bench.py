@@ -161,12 +161,16 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
     timer = Timer(torch)
 
     # a plain copy of known size (counter calibration for FETCH/WRITE_SIZE)
+    copy_gbs = None
     if args.copy_calib_mb > 0:
         a = torch.empty(args.copy_calib_mb << 18, dtype=torch.float32, device=dev)
         a.fill_(1.0)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        cms = timer(lambda: b.copy_(a), 10, 2)
+        copy_gbs = 2 * a.numel() * 4 / (cms * 1e-3) / 1e9      # read + write
+        log(f"device copy of {args.copy_calib_mb} MiB: {copy_gbs:.0f} GB/s")
         del a, b
 
     def timed(factors):
@@ -191,6 +195,27 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         f"{[round(m / max(c, 1), 4) for m, c in per_remap]}")
     sweep_bytes = sum(b_alg_mode(dims, nnz, R, n, 4) for n in range(N))
     value = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    # per-step distribution, and one sweep after a 512 MiB scratch write
+    # (factor rows no longer in L2 or the Infinity Cache)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a0, a1 in ev:
+        a0.record()
+        plan.mttkrp_all_modes(f32, outs)
+        a1.record()
+    torch.cuda.synchronize()
+    step_ms = sorted(a0.elapsed_time(a1) for a0, a1 in ev)
+    scratch = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+    scratch.fill_(0.5)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    plan.mttkrp_all_modes(f32, outs)
+    c1.record()
+    torch.cuda.synchronize()
+    cold_ms = c0.elapsed_time(c1)
+    del scratch
+    log(f"per-step median {step_ms[len(step_ms) // 2]:.3f} ms, min {step_ms[0]:.3f} ms; "
+        f"cold-cache sweep {cold_ms:.3f} ms")
 
     def kstats(times, bytes_of):
         ms = sum(m for m, _ in times)
@@ -252,6 +277,41 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
             als["oracle_fit"] = ofit
         als["bf16_speedup_vs_fp32"] = round(als["fp32"]["sweep_ms"] / als["bf16"]["sweep_ms"], 3)
 
+    ablations = {}
+    if args.rank_sweep:
+        # time against rank (Sec. V: time grows with R): same tensor, N(0,1)
+        # factors of each rank, FP32
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        rows = []
+        for Rk in [int(x) for x in args.rank_sweep.split(",")]:
+            Fk = [torch.randn((d, Rk), generator=gen, device=dev) for d in dims]
+            pk = Plan(idx, vals, dims, Rk, g=args.g)
+            ok = [torch.empty((d, Rk), dtype=torch.float32, device=dev) for d in dims]
+            mk = timer(lambda: pk.mttkrp_all_modes(Fk, ok), args.steps, args.warmup)
+            bk = sum(b_alg_mode(dims, nnz, Rk, n, 4) for n in range(N))
+            rows.append({"rank": Rk, "sweep_ms": round(mk, 4),
+                         "alg_GBs": round(bk / (mk * 1e-3) / 1e9, 1),
+                         "ms_per_rank_unit": round(mk / Rk, 5)})
+            log(f"rank {Rk}: sweep {mk:.3f} ms")
+            del pk, ok, Fk
+        ablations["rank_sweep"] = rows
+    if args.g_sweep:
+        # shard size g (Sec. III-C, V-A): plan time and sweep time
+        rows = []
+        for gk in [int(x) for x in args.g_sweep.split(",")]:
+            torch.cuda.synchronize()
+            t1 = time.time()
+            pk = Plan(idx, vals, dims, R, g=gk)
+            torch.cuda.synchronize()
+            pms = (time.time() - t1) * 1e3
+            mk = timer(lambda: pk.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
+            rows.append({"g": gk, "plan_ms": round(pms, 1), "sweep_ms": round(mk, 4),
+                         "shards": [pk.info(_abi.INFO_NSHARDS, n) for n in range(N)]})
+            log(f"g {gk}: plan {pms:.1f} ms, sweep {mk:.3f} ms")
+            del pk
+        ablations["g_sweep"] = rows
+
     del idx, vals
     cpu = None
     if not args.no_cpu_baseline:
@@ -301,8 +361,64 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
         "cp_als": als,
+        "sweep_ms_median": round(step_ms[len(step_ms) // 2], 4),
+        "sweep_ms_min": round(step_ms[0], 4),
+        "cold_cache_sweep_ms": round(cold_ms, 4),
+        "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
+        "remap_share": {
+            "of_sweep_time": round(sum(m for m, _ in per_remap) / max(sum(c for _, c in per_remap), 1)
+                                   * N / sweep_ms, 4),
+            "of_alg_bytes": round(sum(nnz * rec_bytes(N) for _ in range(N)) / sweep_bytes, 4)},
+        "ablations": ablations or None,
     }
     return rec
+
+
+# ---------------------------------------------------------------- CP-ALS run
+def als_recovery(torch, dev, Plan, D, R=16, seed=20230916 + 6, max_sweeps=300, tol=1e-4):
+    """CP-ALS to convergence on a fully stored D x D x D tensor of planted
+    rank R (N(0,1) factors; entries in FP32), from an independent N(0,1)
+    start.  Pinned by the planted truth: fit -> 1 and every planted column
+    matched (|cos| of normalised columns)."""
+    rng = np.random.default_rng(seed)
+    dims = (D, D, D)
+    true = [rng.standard_normal((D, R)) for _ in range(3)]
+    # X[i, j, k] = sum_r A0[i, r] A1[j, r] A2[k, r], built as A0 (A2 (.) A1)^T
+    kr = (true[2][:, None, :] * true[1][None, :, :]).reshape(D * D, R)   # row k*D + j
+    vals = (true[0] @ kr.T).reshape(-1).astype(np.float32)                # q = i*D*D + k*D + j
+    del kr
+    q = np.arange(D * D * D, dtype=np.int64)
+    idx = np.stack([q // (D * D), q % D, (q // D) % D]).astype(np.int32)
+    del q
+    nnz = idx.shape[1]
+    t0 = time.time()
+    plan = Plan(torch.from_numpy(idx).to(dev), torch.from_numpy(vals).to(dev), dims, R)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - t0) * 1e3
+    del idx, vals
+    init = [rng.standard_normal((D, R)).astype(np.float32) for _ in range(3)]
+    facs = [torch.from_numpy(f).to(dev) for f in init]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lam, fits = plan.cp_als(facs, max_sweeps=max_sweeps, tol=tol)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    fits = fits.cpu().numpy()
+    cong = 1.0
+    for n in range(3):
+        a = facs[n].cpu().numpy().astype(np.float64)
+        a /= np.linalg.norm(a, axis=0)
+        b = true[n] / np.linalg.norm(true[n], axis=0)
+        cong = min(cong, float(np.abs(a.T @ b).max(axis=0).min()))
+    out = {"dims": list(dims), "nnz": int(nnz), "rank": R, "plan_ms": round(plan_ms, 1),
+           "sweeps": int(len(fits)), "final_fit": float(fits[-1]),
+           "fit_after_sweeps_1_2_5_10": [float(fits[k - 1]) for k in (1, 2, 5, 10)
+                                         if k <= len(fits)],
+           "total_ms": round(ms, 1), "ms_per_sweep": round(ms / len(fits), 3),
+           "min_column_congruence": round(cong, 6), "tol": tol}
+    log(f"CP-ALS recovery {out}")
+    return out
 
 
 # ---------------------------------------------------------------- CP loss
@@ -449,6 +565,13 @@ def main():
                     help="nonzeros the CPU oracle baseline processes at most")
     ap.add_argument("--copy-calib-mb", type=int, default=256,
                     help="size of a plain device copy run for counter calibration")
+    ap.add_argument("--rank-sweep", default="",
+                    help="comma-separated ranks: sweep time against R on the same tensor")
+    ap.add_argument("--g-sweep", default="",
+                    help="comma-separated shard sizes g: plan and sweep time against g")
+    ap.add_argument("--als-recovery", type=int, default=0, metavar="D",
+                    help="after the main run: CP-ALS to convergence on a fully stored "
+                         "planted rank-16 D x D x D tensor (D = 368: 49.8M nonzeros)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU "
@@ -470,6 +593,8 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         rec = fn(args, torch, dev, syn, _abi, Plan, oracle)
+        if args.als_recovery > 0:
+            rec["cp_als_recovery"] = als_recovery(torch, dev, Plan, args.als_recovery)
     print(json.dumps(rec), flush=True)
 
 

@@ -174,7 +174,10 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors,
  * max_sweeps sweeps.  The Gram matrices are computed once at the start and
  * then kept current (each mode update refreshes its own), not recomputed
  * every sweep; the results equal max_sweeps calls of cp_als_sweep.
- * Synchronises `stream` after every sweep to read the fit.
+ * Synchronises `stream` after every sweep to read the fit.  The fit comes
+ * from ||X||^2 - 2<X, Xhat> + ||Xhat||^2 with FP32 MTTKRP values, so near
+ * an exact fit it carries noise of about 1e-4: tolerances below that may
+ * never be met there (1e-4 is the usual CP-ALS default).
  *   max_sweeps   >= 1;  tol >= 0 (0: run max_sweeps sweeps).
  *   d_fit_trace  device double[max_sweeps] or NULL: the fit after each sweep.
  *   sweeps, fit  host out (nullable): sweeps run and the last fit.

