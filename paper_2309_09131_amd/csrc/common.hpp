@@ -33,7 +33,7 @@ __device__ __forceinline__ void store_rec(uint32_t *__restrict__ buf, int64_t i,
     *reinterpret_cast<Rec<N> *>(buf + i * (N + 1)) = r;
 }
 
-// Streaming variants (non-temporal hint, per dword) for the record stream.
+// Streaming variant (non-temporal hint, per dword) for a read-once record stream.
 template <int N>
 __device__ __forceinline__ Rec<N> load_rec_nt(const uint32_t *__restrict__ buf, int64_t i)
 {
@@ -42,14 +42,6 @@ __device__ __forceinline__ Rec<N> load_rec_nt(const uint32_t *__restrict__ buf, 
 #pragma unroll
     for (int k = 0; k < N + 1; ++k) r.w[k] = __builtin_nontemporal_load(p + k);
     return r;
-}
-
-template <int N>
-__device__ __forceinline__ void store_rec_nt(uint32_t *__restrict__ buf, int64_t i, const Rec<N> &r)
-{
-    uint32_t *p = buf + i * (N + 1);
-#pragma unroll
-    for (int k = 0; k < N + 1; ++k) __builtin_nontemporal_store(r.w[k], p + k);
 }
 
 // Coordinate `n` (runtime) of a record without dynamic register indexing,

@@ -32,16 +32,16 @@ hipError_t launch_one(const Args &a, int kind, unsigned grid, hipStream_t s)
     // separate instantiations with and without the in-kernel remap
     if (kind == KIND_MTTKRP && a.rout)
         hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, false, true>), dim3(grid),
-                           dim3(256), 0, s, a);
+                           dim3(MTT_WAVES * 64), 0, s, a);
     else if (kind == KIND_MTTKRP)
         hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, false, false>), dim3(grid),
-                           dim3(256), 0, s, a);
+                           dim3(MTT_WAVES * 64), 0, s, a);
     else if (kind == KIND_RESID && a.rout)
         hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, true, true>), dim3(grid),
-                           dim3(256), 0, s, a);
+                           dim3(MTT_WAVES * 64), 0, s, a);
     else if (kind == KIND_RESID)
         hipLaunchKernelGGL((mttkrp_kernel<NM, FT, LANES, V, STRIDED, true, false>), dim3(grid),
-                           dim3(256), 0, s, a);
+                           dim3(MTT_WAVES * 64), 0, s, a);
     else
         hipLaunchKernelGGL((loss_kernel<NM, FT, LANES, V, STRIDED>), dim3(grid), dim3(256), 0,
                            s, a);

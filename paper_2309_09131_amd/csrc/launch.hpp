@@ -25,6 +25,10 @@ struct Args {
     double *partial;          // loss forward: one double per shard
 };
 
+// Waves (one shard each) per workgroup of the MTTKRP kernels (1, 2 and 4
+// measured equal; 8 and 12 slower).
+constexpr int MTT_WAVES = 4;
+
 // Lane configuration: contiguous (lanes = nextpow2(R / V); j = 2: V = 32
 // bytes of factor row per lane, j = 1: 16 bytes) or strided (64 lanes,
 // j = ceil(R / 64) ranks each).

@@ -214,16 +214,14 @@ __device__ __forceinline__ float slot_sum(float v)
 // once.  The first row of each run (head) and the last (tail) are then
 // joined across slots with one segmented scan per shard.
 template <int N, typename FT, int LANES, int V, bool STRIDED, bool RESID, bool FUSE>
-__global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
+__global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
-#ifdef MK_U
-    constexpr int U = MK_U;
-#else
+    // nonzeros per step of a lane group: 4 measured fastest (2 and 3 keep
+    // fewer gathers in flight; 8 runs out of registers)
     constexpr int U = 4;
-#endif
     const int lane = threadIdx.x & 63;
-    const int sidx = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int sidx = blockIdx.x * MTT_WAVES + (threadIdx.x >> 6);
     if (sidx >= a.nshards) return;                         // whole wave
     const int shard = a.order ? a.order[sidx] : sidx;
     const int start = a.shards[3 * shard];
@@ -266,11 +264,7 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
     // products are the same.  NR = 1, or 2 from five modes on (measured;
     // with four modes the registers of a second input cost more occupancy
     // than the loads save, and with BF16 factors even the first does).
-#ifdef MK_NR
-    constexpr int NR0 = MK_NR;
-#else
     constexpr int NR0 = N >= 5 ? 2 : 1;
-#endif
     constexpr int NR = (sizeof(FT) == 4 && N > 2) ? (N - 2 < NR0 ? N - 2 : NR0) : 0;
     constexpr bool REUSE = NR > 0;
     float xp[NR > 0 ? NR : 1][V];
@@ -378,11 +372,7 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(Args a)
             for (int u = 0; u < U; ++u) dst[u] = a.perm[ok[u] ? s0 + k + u : start];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-#ifdef MK_NT_REMAP
-                if (ok[u] && sub == 0) store_rec_nt<N>(a.rout, dst[u], rc[u]);
-#else
                 if (ok[u] && sub == 0) store_rec<N>(a.rout, dst[u], rc[u]);
-#endif
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -528,16 +518,9 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
 template <int N>
 __host__ __device__ constexpr int remap_rt()
 {
-#ifdef MK_RT
-    constexpr int RT0 = MK_RT;
-#else
+    // 16 measured fastest of 8, 12, 16, 24 and 30
     constexpr int RT0 = 16;
-#endif
-#ifdef MK_LDSKB
-    constexpr int RTC = (MK_LDSKB * 1024) / (256 * (4 * (N + 1) + 4));
-#else
     constexpr int RTC = (96 * 1024) / (256 * (4 * (N + 1) + 4));
-#endif
     return RT0 < RTC ? RT0 : RTC;
 }
 
@@ -549,11 +532,7 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
 {
     constexpr int RT = remap_rt<N>();
     constexpr int RB = 256 * RT;
-#ifdef MK_NB
-    constexpr int NB = MK_NB;
-#else
     constexpr int NB = 1024;              // buckets
-#endif
     __shared__ Rec<N> srec[RB];
     __shared__ int32_t sdst[RB];
     __shared__ int32_t cnt[NB];

@@ -661,7 +661,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.gscale = gscale;
     a.partial = p->rt<double>(L.rt_partial);
     const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
-    const unsigned grid = (unsigned)((p->nshards[n] + 3) / 4);
+    const int wpb = kind == mk::KIND_LOSS ? 4 : mk::MTT_WAVES;   // shards per workgroup
+    const unsigned grid = (unsigned)((p->nshards[n] + wpb - 1) / wpb);
     const int pk = kind == mk::KIND_MTTKRP  ? MTTKRP_PROF_MTTKRP
                    : kind == mk::KIND_RESID ? MTTKRP_PROF_RESID
                                             : MTTKRP_PROF_LOSS;
