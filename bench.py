@@ -67,6 +67,19 @@ def b_min_mttkrp_kernel(dims, nnz, R, n, sf):
         + dims[n] * R * 4
 
 
+def host_cpu():
+    """Host CPU model and logical core count (the oracle itself uses one)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count()}
+
+
 def source_sha():
     h = hashlib.sha256()
     here = os.path.join(ROOT, "paper_2309_09131_amd", "csrc")
@@ -324,7 +337,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         sb = sum(b_alg_mode(dims, S, R, n, 4) for n in range(N))
         what = "all" if S == nnz else f"the first {S} (in generation order) of {nnz}"
         cpu = {"value": round(sb / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sweep_s": round(cs, 2),
+               "sweep_s": round(cs, 2), "host": host_cpu(),
                "sample": f"FP64 oracle MTTKRP along all {N} modes over {what} nonzeros, "
                          f"single thread; value = paper-model bytes of that sample / time"}
         log(f"oracle sweep {cs:.1f} s on one core ({S} nonzeros)")
@@ -347,6 +360,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                      "alg_bytes_per_launch": int(mk_bytes),
                      "compulsory_bytes_per_launch": int(mk_min),
                      "compulsory_frac": round(mk_min / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic_GBs": round(traffic / (mk_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "note": "algorithmic bytes count every gathered factor row "
                              "(paper's traffic model); most gathers hit L2/MALL"},
         "remap_kernel": {"ms_per_launch": round(rm_ms, 4),
@@ -524,6 +538,7 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
         cs = time.time() - tc
         sb = Sc * (E + N * R * 4) + N * Sc * (2 * E + N * R * 4)
         cpu = {"value": round(sb / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "host": host_cpu(),
                "sample": f"FP64 oracle loss + gradient over the first {Sc} of {nnz} nonzeros, "
                          f"single thread", "seconds": round(cs, 2)}
     return {
