@@ -15,7 +15,12 @@ Other workloads (explicit runs; parity and reporting, not the headline):
   --config 5  2e6x1e6x1e5x5e3x500, 200M nnz, R=16: full CP-ALS sweep, FP32
               and BF16
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the sweep metric, the roofline of the per-mode MTTKRP
+kernel (algorithmic bytes per launch / mean launch time from HIP events, the
+compulsory-byte fraction, and the DRAM bytes from the committed rocprofv3
+counter summary when it was taken on the current kernel sources), the remap
+kernel, the FP64 oracle's single-core rate on a bounded sample, the BF16
+sweep with its errors, and the optional ablations.
 """
 from __future__ import annotations
 
@@ -589,8 +594,9 @@ def main():
                          "planted rank-16 D x D x D tensor (D = 368: 49.8M nonzeros)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
-              "path (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
+              "(the super-shards of a mode would be split over GPUs, with the "
+              "remap as an all-to-all between modes; not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
