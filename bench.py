@@ -28,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -86,11 +87,17 @@ def host_cpu():
 
 
 def source_sha():
+    """Hash of the MTTKRP kernel sources with comments and blank lines
+    removed: a comment edit does not make the counter summary stale."""
     h = hashlib.sha256()
     here = os.path.join(ROOT, "paper_2309_09131_amd", "csrc")
     for f in ("common.hpp", "mttkrp_kernels.hpp", "inst.hpp", "launch.hpp"):
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(here, f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code.strip():
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -1,27 +1,32 @@
-// Per-mode sparse MTTKRP with fused dynamic remapping, the residual
-// (loss-gradient) variant, the sampled-loss forward, and the standalone
-// remap, templated on the number of modes N and the factor storage type.
+// Per-mode sparse MTTKRP (optionally with the dynamic remap in the same
+// pass), the residual (loss-gradient) variant, the sampled-loss forward, and
+// the standalone remap, templated on the number of modes N and the factor
+// storage type.
 //
 // Work decomposition.  The tensor buffer holds layout L_n: nonzeros
 // contiguous by output row c_n (Sec. III-B).  The plan cuts it into shards
 // of at most g nonzeros that never cross a super-shard (Sec. III-A); one
 // wave64 processes one shard.  Lanes run along the rank: a nonzero is
-// handled by LANES lanes holding V consecutive ranks each (16-byte factor
-// gathers), so one step covers SW = 64/LANES consecutive nonzeros.
+// handled by LANES lanes holding V consecutive ranks each (16 or 32 bytes
+// of factor row per lane), so one step covers SW = 64/LANES nonzeros, one
+// per lane group ("slot"); the shard is cut into SW contiguous runs, one per
+// slot.
 //
 // Per nonzero (elementwise update, Sec. II-C / Eq. 4): gather the N-1 input
 // factor rows, form their Hadamard product in registers, scale by the
-// value.  Rows are reduced with a segmented inclusive scan across the SW
-// slots of a step plus a running carry across steps, so every output row is
-// produced by one wave in a fixed order: rows wholly inside the shard are
-// written directly, the shard's first row (if it began in an earlier shard)
-// and last row (if it continues) go to a per-shard partial slot that the
-// carry fix-up kernel adds in shard order.  No global atomics anywhere
-// (lock-free ownership of output rows, Sec. IV).
+// value.  Rows that start and end inside a slot's run are accumulated in
+// registers and written at once; the runs' first and last rows are joined
+// by one segmented scan over the slots, so every output row is produced by
+// one wave in a fixed order.  The shard's first row (if it began in an
+// earlier shard) and last row (if it continues) go to a per-shard partial
+// slot that the carry fix-up kernel adds in shard order.  No global atomics
+// anywhere (lock-free ownership of output rows, Sec. IV).
 //
-// Remap (Alg. "Dynasor", store into the next mode's shard): lane 0 of each
-// slot copies the whole record to L_{n+1}[P_n[e]], the slot precomputed by
-// the plan, in the same pass (Sec. V-B: same agent).
+// Remap (Alg. "Dynasor", store into the next mode's shard): by default a
+// separate kernel right after the MTTKRP (remap_kernel, below); with the
+// FUSE form, lane 0 of each slot copies the whole record to L_{n+1}[P_n[e]],
+// the slot precomputed by the plan, in the MTTKRP pass itself (the paper's
+// same-agent form, Sec. V-B).
 #pragma once
 #include "common.hpp"
 #include "launch.hpp"
