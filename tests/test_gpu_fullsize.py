@@ -4,7 +4,8 @@ Workload 1 (100K nonzeros) is compared element by element with the FP64
 oracle.  Workload 2 (20M nonzeros), in the launch configuration the
 benchmark times (default plan options, FP32 factors, all-mode sweep), is
 compared on sampled output rows that the oracle computes one by one, and
-on layout invariants that hold at any size.
+on layout invariants that hold at any size.  A mode of 2^26 rows at R = 64
+checks 64-bit addressing (factor and output offsets up to 2^32 elements).
 """
 import numpy as np
 import pytest
@@ -85,3 +86,49 @@ def test_results_on_a_side_stream_match_default_stream():
     for a, b in zip(ref, outs):
         assert torch.equal(a, b)
     assert torch.isfinite(total)
+
+
+def test_huge_mode_offsets_beyond_2_31_elements():
+    """A mode of 2^26 rows with R = 64: factor and output offsets reach 2^32
+    elements (16 GiB per matrix), so every address computed from a row id
+    must be 64-bit.  The nonzeros touch a few hundred rows spread over the
+    whole range, including the first and the last; the oracle runs on the
+    same tensor with those rows renumbered 0..K-1 (MTTKRP does not depend on
+    row names), and the untouched rows of the huge output must be +0.0."""
+    I0, R = 1 << 26, 64
+    dims = (I0, 300, 200)
+    rng = np.random.default_rng(2026)
+    rows = np.unique(np.concatenate([[0, I0 - 1, (1 << 25) + 3],
+                                     rng.integers(0, I0, 400)])).astype(np.int64)
+    K = len(rows)
+    nnz = 50_000
+    c0 = rng.integers(0, K, nnz)
+    idx_small = np.stack([c0, rng.integers(0, 300, nnz), rng.integers(0, 200, nnz)])
+    idx_huge = idx_small.copy()
+    idx_huge[0] = rows[c0]
+    vals = rng.standard_normal(nnz).astype(np.float32)
+    A0 = rng.standard_normal((K, R)).astype(np.float32)
+    A1 = rng.standard_normal((300, R)).astype(np.float32)
+    A2 = rng.standard_normal((200, R)).astype(np.float32)
+    d = dev()
+    say("huge mode: allocating 2 x 16 GiB")
+    a0 = torch.zeros((I0, R), dtype=torch.float32, device=d)
+    rows_t = torch.from_numpy(rows).to(d)
+    a0[rows_t] = torch.from_numpy(A0).to(d)
+    facs = [a0, torch.from_numpy(A1).to(d), torch.from_numpy(A2).to(d)]
+    p = Plan(torch.from_numpy(idx_huge.astype(np.int32)).to(d), torch.from_numpy(vals).to(d),
+             dims, R)
+    outs = p.mttkrp_all_modes(facs)
+    torch.cuda.synchronize()
+    dims_small = (K, 300, 200)
+    idx_s = idx_small.astype(np.int32)
+    for n in range(3):
+        ref, rabs = oracle.mttkrp(dims_small, idx_s, vals, [A0, A1, A2], n, with_abs=True)
+        got = outs[n][rows_t].cpu().numpy() if n == 0 else outs[n].cpu().numpy()
+        check_close(got, ref, rabs, FP32_TOL, f"mode {n}")
+    # untouched rows of the 2^26-row output: exactly zero
+    probe = torch.from_numpy(np.setdiff1d(rng.integers(0, I0, 2000), rows)).to(d)
+    assert torch.count_nonzero(outs[0][probe]).item() == 0
+    assert torch.count_nonzero(outs[0][1:rows[1]]).item() == 0
+    del outs, a0, facs, p
+    torch.cuda.empty_cache()
