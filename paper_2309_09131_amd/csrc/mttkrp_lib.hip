@@ -835,8 +835,11 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
     int oc = 0;
     for (int n = 0; n < N; ++n) {
         const int nx = (n + 1) % N;
-        hipLaunchKernelGGL(plan::row_ptr_kernel, dim3(grid_for(nnz + 1)), dim3(256), 0, s,
-                           d_idx + n * nnz, ob[oc], nnz, (int32_t)L.dims[n], p->rp(n));
+        // c_n in layout order (sorted) into kb[1], free until the sort below
+        hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + n * nnz,
+                           ob[oc], nnz, kb[1], vb[1], 1);
+        hipLaunchKernelGGL(plan::row_ptr_kernel, dim3(grid_for(L.dims[n] + 1)), dim3(256), 0, s,
+                           kb[1], nnz, (int32_t)L.dims[n], p->rp(n));
         hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + nx * nnz,
                            ob[oc], nnz, kb[0], vb[0], 1);
         int which = 0;

@@ -193,16 +193,23 @@ __global__ void invert_kernel(const int32_t *__restrict__ q, int64_t n, int32_t 
     }
 }
 
-// Row pointers of a layout sorted by coordinate c = coord[o[j]]:
-// row_ptr[r] = first j with c >= r; every entry written exactly once.
-__global__ void row_ptr_kernel(const int32_t *__restrict__ coord, const int32_t *__restrict__ o,
-                               int64_t n, int32_t I, int32_t *__restrict__ row_ptr)
+// Row pointers of a layout sorted by the mode's coordinate: row_ptr[r] =
+// first position whose coordinate is >= r (= number of nonzeros with
+// coordinate < r), r = 0..I, by a binary search of the coordinates in
+// layout order.  One thread per row, every entry written once, so a long
+// run of empty rows costs no more than any other rows.
+__global__ void row_ptr_kernel(const int32_t *__restrict__ sorted, int64_t n, int32_t I,
+                               int32_t *__restrict__ row_ptr)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= n;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        int32_t cur = (j < n) ? coord[o[j]] : I;
-        int32_t prev = (j > 0) ? coord[o[j - 1]] : -1;
-        for (int32_t r = prev + 1; r <= cur; ++r) row_ptr[r] = (int32_t)j;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= I;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n;                 // first position with sorted[pos] >= r
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted[mid] < r) lo = mid + 1;
+            else hi = mid;
+        }
+        row_ptr[r] = (int32_t)lo;
     }
 }
 
