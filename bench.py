@@ -314,12 +314,16 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
             pk = Plan(idx, vals, dims, Rk, g=args.g)
             ok = [torch.empty((d, Rk), dtype=torch.float32, device=dev) for d in dims]
             mk = timer(lambda: pk.mttkrp_all_modes(Fk, ok), args.steps, args.warmup)
+            Fb = [f.to(torch.bfloat16) for f in Fk]
+            mb = timer(lambda: pk.mttkrp_all_modes(Fb, ok), args.steps, args.warmup)
             bk = sum(b_alg_mode(dims, nnz, Rk, n, 4) for n in range(N))
             rows.append({"rank": Rk, "sweep_ms": round(mk, 4),
                          "alg_GBs": round(bk / (mk * 1e-3) / 1e9, 1),
-                         "ms_per_rank_unit": round(mk / Rk, 5)})
-            log(f"rank {Rk}: sweep {mk:.3f} ms")
-            del pk, ok, Fk
+                         "ms_per_rank_unit": round(mk / Rk, 5),
+                         "bf16_sweep_ms": round(mb, 4),
+                         "bf16_speedup": round(mk / mb, 3)})
+            log(f"rank {Rk}: sweep {mk:.3f} ms, bf16 {mb:.3f} ms (x{mk / mb:.2f})")
+            del pk, ok, Fk, Fb
         ablations["rank_sweep"] = rows
     if args.g_sweep:
         # shard size g (Sec. III-C, V-A): plan time and sweep time
