@@ -276,6 +276,19 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                        "error_vs_fp64_oracle": errb, "tolerance": 2e-2}
         log(f"bf16 sweep {bms:.3f} ms (x{sweep_ms / bms:.2f})")
 
+    # the paper's "without remapping" baseline: one tensor copy per mode
+    # layout (N x the memory), so each mode's MTTKRP runs with no remap;
+    # timed here as the MTTKRP of each mode on its own layout
+    ncopy_ms = 0.0
+    for n in range(N):
+        if plan.cur_mode != n:
+            plan.remap(n)
+        ncopy_ms += timer(lambda: plan.mttkrp_mode(n, f32, outs[n], fuse_remap=False),
+                          args.steps, args.warmup)
+    plan.remap(0)
+    torch.cuda.synchronize()
+    log(f"one layout copy per mode (no remap): {ncopy_ms:.3f} ms per sweep")
+
     fused_ms = None
     if not args.no_ablation:
         # the paper's same-agent form: remap written from inside the MTTKRP kernel
@@ -390,6 +403,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "fp32_error_vs_fp64_oracle": err32,
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
+        "layout_copy_per_mode_sweep_ms": round(ncopy_ms, 4),
         "cp_als": als,
         "sweep_ms_median": round(step_ms[len(step_ms) // 2], 4),
         "sweep_ms_min": round(step_ms[0], 4),
