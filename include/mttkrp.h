@@ -121,10 +121,13 @@ mttkrp_status mttkrp_mode(mttkrp_plan_t p, int mode, const void *const *d_factor
                           mttkrp_dtype fdt, float *d_out, int fuse_remap,
                           void *stream);
 
-/* MTTKRP along all modes n = 0..N-1 with fused remapping (Alg. "Dynasor");
- * every mode uses the given factors.  d_out: host array of nmodes device
- * pointers, each I_n x R FP32.  Starts from L_0 (remapping first if needed)
- * and ends in L_0. */
+/* MTTKRP along all modes n = 0..N-1, each followed by the remap into the
+ * next mode's layout (Alg. "Dynasor"); every mode uses the given factors.
+ * d_out: host array of nmodes device pointers, each I_n x R FP32.  The
+ * buffers may overlap (even be one buffer): a pass that writes memory still
+ * being written by an earlier pass waits for it, so each buffer ends up
+ * with the result of the last mode written into it.  Starts from L_0
+ * (remapping first if needed) and ends in L_0. */
 mttkrp_status mttkrp_all_modes(mttkrp_plan_t p, const void *const *d_factors,
                                mttkrp_dtype fdt, float *const *d_out,
                                void *stream);

@@ -166,6 +166,10 @@ struct mttkrp_plan_s {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_seg[2] = {nullptr, nullptr};
     bool seg_pending[2] = {false, false};
+    // output range each pending reduction writes (callers may pass one
+    // buffer for several passes: a later pass must not start before it)
+    const char *seg_out[2] = {nullptr, nullptr};
+    size_t seg_out_bytes[2] = {0, 0};
     bool aux_pending = false;
     int carry_sel = 0;
 
@@ -632,6 +636,18 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     const Layout &L = p->L;
     const int n = p->cur;
     const int64_t rows = L.dims[n];
+    if (kind != mk::KIND_LOSS) {
+        // a pending reduction of an earlier pass that writes into this
+        // pass's output range must finish first
+        const char *o0 = reinterpret_cast<const char *>(out);
+        const size_t ob = (size_t)rows * L.R * sizeof(float);
+        for (int b = 0; b < 2; ++b)
+            if (p->seg_pending[b] && o0 < p->seg_out[b] + p->seg_out_bytes[b] &&
+                p->seg_out[b] < o0 + ob) {
+                HIPCHK(p, hipStreamWaitEvent(s, p->ev_seg[b], 0));
+                p->seg_pending[b] = false;
+            }
+    }
     if (kind != mk::KIND_LOSS && (p->nempty[n] > 0 || L.nnz == 0))
         hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(rows * L.R)), dim3(256), 0, s, out,
                            rows * L.R);
@@ -712,6 +728,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         }
         HIPCHK(p, hipEventRecord(p->ev_seg[cs], p->aux));
         p->seg_pending[cs] = true;
+        p->seg_out[cs] = reinterpret_cast<const char *>(out);
+        p->seg_out_bytes[cs] = (size_t)rows * L.R * sizeof(float);
         p->aux_pending = true;
     }
     if (infuse) {

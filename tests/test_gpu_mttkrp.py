@@ -174,3 +174,23 @@ def test_empty_tensor_gives_zero_outputs():
     outs = p.mttkrp_all_modes(facs)
     for o in outs:
         assert torch.count_nonzero(o) == 0
+
+
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
+def test_one_output_buffer_for_every_mode(flags):
+    """Callers may pass the same buffer as the output of every mode: the
+    split-row reduction of one pass (on the side stream) must finish before
+    the next pass writes the buffer.  After the sweep the buffer holds the
+    last mode's result, equal to the oracle's."""
+    dims, R = (400, 300, 200), 32
+    t = syn.random_tensor(dims, 60000, R, 33, zipf_s=1.4)
+    p, facs = make_plan(t, g=32, flags=flags)   # many rows split across shards
+    assert all(p.info(_abi.INFO_NSPLIT, n) > 0 for n in range(3))
+    big = torch.empty(max(dims) * R, dtype=torch.float32, device=facs[0].device)
+    outs = [big[:d * R].view(d, R) for d in dims]
+    for _ in range(3):
+        big.fill_(float("nan"))
+        p.mttkrp_all_modes(facs, outs)
+        torch.cuda.synchronize()
+        ref, rabs = oracle.mttkrp(dims, t.idx, t.vals, t.factors, 2, with_abs=True)
+        check_close(outs[2].cpu().numpy(), ref, rabs, FP32_TOL, "last mode")
