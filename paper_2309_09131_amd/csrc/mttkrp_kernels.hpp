@@ -223,7 +223,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
     // nonzeros per step of a lane group: 4 measured fastest (2 and 3 keep
-    // fewer gathers in flight; 8 runs out of registers)
+    // fewer gathers in flight; 8 halves the waves per SIMD and is slower)
     constexpr int U = 4;
     const int lane = threadIdx.x & 63;
     const int sidx = blockIdx.x * MTT_WAVES + (threadIdx.x >> 6);
@@ -283,9 +283,9 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     // Records are loaded once per lane group, not once per lane: lane `sub`
     // of a slot loads records sub, sub + LANES, ... of the slot's next U
     // nonzeros (RPL per lane), and the words are then broadcast inside the
-    // slot with cross-lane moves.  The vector-memory address unit is the
-    // limiter of this kernel, so duplicate loads are expensive.  The next
-    // group's records are loaded while the current group computes.
+    // slot with cross-lane moves.  The vector-memory path (misses in flight
+    // per CU) limits this kernel, so duplicate loads are expensive.  The
+    // next group's records are loaded while the current group computes.
     constexpr int RPL = (U + LANES - 1) / LANES;
     Rec<N> nxt[RPL];
 #pragma unroll
