@@ -288,3 +288,27 @@ def test_cp_als_recovers_planted_dense_tensor(dims, R, seed):
     for _ in range(150):
         F, _, ofit, _, _ = oracle.cp_als_sweep(dims, idx, vals, F)
     assert ofit > 1 - 1e-5
+
+
+@pytest.mark.parametrize("case", LOSS_CASES[:3] + LOSS_CASES[4:])
+def test_loss_and_gradient_bf16_factors(case):
+    """BF16-stored factors: against the oracle on the BF16-rounded factors
+    (accumulation error only) within the FP32 tolerance, and against the
+    oracle on the FP32 factors (storage rounding included) within 2e-2."""
+    dims, nnz, R, seed, g = case
+    say("loss bf16 case", case)
+    t = syn.random_tensor(dims, nnz, R, seed, factors="uniform")
+    idx, vals, facs = to_dev(t, torch.bfloat16)
+    p = Plan(idx, vals, dims, R, g=g)
+    loss, grads = p.cp_loss_grad(facs)
+    torch.cuda.synchronize()
+    fb = [bf16_round(f) for f in t.factors]
+    Lb, Gb = oracle.cp_loss_grad(dims, t.idx, t.vals, fb)
+    assert abs(loss.item() - Lb) <= FP32_TOL * abs(Lb)
+    refs = _grad_ref(t, fb)
+    L32, G32 = oracle.cp_loss_grad(dims, t.idx, t.vals, [f.astype(np.float64) for f in t.factors])
+    assert abs(loss.item() - L32) <= BF16_TOL * abs(L32)
+    for k in range(len(dims)):
+        gk = grads[k].cpu().numpy()
+        check_close(gk, refs[k][0], refs[k][1], FP32_TOL, f"bf16 grad {k}")
+        assert np.linalg.norm(gk - G32[k]) <= BF16_TOL * np.linalg.norm(G32[k])
