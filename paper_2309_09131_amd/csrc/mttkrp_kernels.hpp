@@ -562,10 +562,10 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
             const bool ok = i < nnz;
             // Read-once streams are loaded non-temporal, so they do not
             // evict the partly written destination lines that wait in L2 for
-            // their other records.  Records only when one 16-byte load (or
-            // two) covers them: a record read by a 16-byte and a 4-byte load
-            // touches its lines twice, and a streamed line can be gone before
-            // the second load (measured slower with 4 and 5 modes).
+            // their other records.  Records only when one or two 16-byte
+            // loads cover them (3 and 7 modes): for 20- and 24-byte records
+            // non-temporal loads measured 15-45% slower, also when the chunk
+            // was first staged so that every line is read once.
             if constexpr ((N + 1) % 4 == 0) r[k] = load_rec_nt<N>(rin, ok ? i : 0);
             else r[k] = load_rec<N>(rin, ok ? i : 0);
             d[k] = ok ? __builtin_nontemporal_load(perm + i) : -1;
