@@ -390,6 +390,8 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                      "compulsory_bytes_per_launch": int(mk_min),
                      "compulsory_frac": round(mk_min / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic_GBs": round(traffic / (mk_ms * 1e-3) / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                     if traffic else None,
                      "note": "algorithmic bytes count every gathered factor row "
                              "(paper's traffic model); most gathers hit L2/MALL"},
         "remap_kernel": {"ms_per_launch": round(rm_ms, 4),
