@@ -10,10 +10,10 @@
  * along every mode n (the elementwise spMTTKRP update of Sec. II-C and
  * Eq. 4 of Wijeratne, Kannan, Prasanna, "Dynasor", arXiv 2309.09131), with
  * the paper's dynamic tensor remapping (Sec. III-B): the nonzeros are kept
- * in one buffer ordered for the mode being computed and, while mode n is
- * computed, copied into the order of mode (n+1) mod N (Alg. "Dynasor",
- * dynamic remapping store), so that two tensor-sized buffers serve all
- * modes.  Around it: one CP-ALS sweep (Alg. "cp-als"), and the sampled CP
+ * in one buffer ordered for the mode being computed and, once mode n is
+ * computed (or during it, in the fused form), copied into the order of mode
+ * (n+1) mod N (Alg. "Dynasor", dynamic remapping store), so that two
+ * tensor-sized buffers serve all modes.  Around it: one CP-ALS sweep (Alg. "cp-als"), and the sampled CP
  * loss sum_e (x_e - sum_r prod_n A_n(c_n(e), r))^2 with its gradient.
  *
  * Conventions for every entry point
@@ -21,7 +21,9 @@
  *     that is current when the call is made); all others are host pointers.
  *   - The caller owns every device allocation (workspace, tensor, factors,
  *     outputs).  The library never allocates device memory; a plan owns
- *     only a small host object and HIP events.
+ *     only a small host object, HIP events and a non-blocking side stream
+ *     of default priority (the reduction of rows split across shards runs
+ *     there, ordered by events; every call joins it before returning).
  *   - `stream` is a hipStream_t passed as void* (NULL = legacy default
  *     stream).  Except mttkrp_plan (synchronous), calls only enqueue work
  *     on `stream` and return; a plan must be used by one stream at a time.
