@@ -23,7 +23,7 @@
  *     outputs).  The library never allocates device memory; a plan owns
  *     only a small host object, HIP events and a non-blocking side stream
  *     of default priority (the reduction of rows split across shards runs
- *     there, ordered by events; every call joins it before returning).
+ *     there, ordered by events; every call makes `stream` wait for it).
  *   - `stream` is a hipStream_t passed as void* (NULL = legacy default
  *     stream).  Except mttkrp_plan (synchronous), calls only enqueue work
  *     on `stream` and return; a plan must be used by one stream at a time.
