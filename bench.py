@@ -186,17 +186,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
     timer = Timer(torch)
 
     # a plain copy of known size (counter calibration for FETCH/WRITE_SIZE)
-    copy_gbs = None
-    if args.copy_calib_mb > 0:
-        a = torch.empty(args.copy_calib_mb << 18, dtype=torch.float32, device=dev)
-        a.fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        cms = timer(lambda: b.copy_(a), 10, 2)
-        copy_gbs = 2 * a.numel() * 4 / (cms * 1e-3) / 1e9      # read + write
-        log(f"device copy of {args.copy_calib_mb} MiB: {copy_gbs:.0f} GB/s")
-        del a, b
+    copy_gbs = device_copy(torch, dev, args.copy_calib_mb, timer)
 
     def timed(factors):
         # the sweep time without per-kernel events, then the same steps again
@@ -421,6 +411,23 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
 
 
 # ---------------------------------------------------------------- CP-ALS run
+def device_copy(torch, dev, mb, timer):
+    """A plain device copy of `mb` MiB: its bandwidth, and the reference the
+    FETCH_SIZE / WRITE_SIZE counter runs are calibrated against."""
+    if mb <= 0:
+        return None
+    a = torch.empty(mb << 18, dtype=torch.float32, device=dev)
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    cms = timer(lambda: b.copy_(a), 10, 2)
+    gbs = 2 * a.numel() * 4 / (cms * 1e-3) / 1e9      # read + write
+    log(f"device copy of {mb} MiB: {gbs:.0f} GB/s")
+    del a, b
+    return gbs
+
+
 def als_recovery(torch, dev, Plan, D, R=16, seed=20230916 + 6, max_sweeps=300, tol=1e-4):
     """CP-ALS to convergence on a fully stored D x D x D tensor of planted
     rank R (N(0,1) factors; entries in FP32), from an independent N(0,1)
@@ -482,6 +489,7 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
     torch.cuda.synchronize()
     plan_ms = (time.time() - tp) * 1e3
     timer = Timer(torch)
+    copy_gbs = device_copy(torch, dev, args.copy_calib_mb, timer)
     fac = [torch.from_numpy(f).to(dev).requires_grad_(True) for f in T.factors]
 
     def step():
@@ -513,6 +521,11 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
     r_launch = sum(c for _, c in resid)
     r_bytes = sum((nnz * (E + N * R * 4) + dims[n] * R * 4) * resid[n][1] for n in range(N))
     r_gbs = r_bytes / (r_ms * 1e-3) / 1e9
+    ctr = os.path.join(ROOT, "profiles", f"resid_kernel_{w.name}_counters.txt")
+    fetch = counter_traffic(ctr, "fetch_bytes_per_launch")
+    write = counter_traffic(ctr, "write_bytes_per_launch")
+    traffic = (fetch + write) if (fetch is not None and write is not None) else None
+    r_kms = r_ms / r_launch
     l_gbs = nnz * (E + N * R * 4) * lossk[1] / (lossk[0] * 1e-3) / 1e9
     log(f"residual MTTKRP kernel {r_ms / r_launch:.4f} ms/launch ({r_gbs:.0f} GB/s), "
         f"loss kernel {lossk[0] / lossk[1]:.4f} ms ({l_gbs:.0f} GB/s), remap "
@@ -582,7 +595,10 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
                    "step": "sampled CP loss forward + autograd backward to all factors",
                    "plan_ms": round(plan_ms, 1)},
         "roofline": {"bound": "hbm", "achieved": round(r_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(r_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_GBs": round(traffic / (r_kms * 1e-3) / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / (r_kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                     if traffic else None,
                      "kernel": "mk::mttkrp_kernel residual form (loss gradient, per mode)",
                      "kernel_ms_per_launch": round(r_ms / r_launch, 4),
                      "alg_bytes_per_launch": int(r_bytes / r_launch),
@@ -592,6 +608,7 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
                         "alg_bytes_per_launch": int(nnz * (E + N * R * 4)),
                         "achieved_GBs": round(l_gbs, 1)},
         "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
+        "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "checks": checks,
     }
 
