@@ -469,8 +469,9 @@ static mttkrp_status radix_sort(mttkrp_plan_t p, int32_t *k0, int32_t *v0, int32
         hipLaunchKernelGGL(plan::scan_sums, dim3(1), dim3(256), 0, s, sums, nchunks);
         hipLaunchKernelGGL(plan::scan_apply, dim3((unsigned)nchunks), dim3(256), 0, s, hist, hlen,
                            sums, hscan);
-        hipLaunchKernelGGL(plan::radix_scatter, dim3((unsigned)ntiles), dim3(64), 0, s, K[cur],
-                           Vv[cur], n, shift, hscan, (int)ntiles, K[cur ^ 1], Vv[cur ^ 1]);
+        hipLaunchKernelGGL(plan::radix_scatter_tile, dim3((unsigned)ntiles), dim3(256), 0, s,
+                           K[cur], Vv[cur], n, shift, hscan, (int)ntiles, K[cur ^ 1],
+                           Vv[cur ^ 1]);
         HIPCHK(p, hipGetLastError());
         cur ^= 1;
     }

@@ -139,45 +139,100 @@ __global__ __launch_bounds__(256) void scan_apply(const int32_t *__restrict__ in
     }
 }
 
-// Stable scatter of one tile by one wave, 64 rounds of 64 consecutive items:
-// items with equal digits keep their order (rank via ballot matching).
-__global__ __launch_bounds__(64) void radix_scatter(const int32_t *__restrict__ kin,
-                                                   const int32_t *__restrict__ vin, int64_t n,
-                                                   int shift, const int32_t *__restrict__ offs,
-                                                   int ntiles, int32_t *__restrict__ kout,
-                                                   int32_t *__restrict__ vout)
+// Stable scatter of one tile by four waves, with coalesced writes.  Wave w
+// ranks the items [w*1024, (w+1)*1024) of the tile in 16 rounds of 64 with
+// ballot matching (equal digits keep their order) and counts its digits;
+// the tile's items are then placed in LDS in (digit, position) order and
+// written out so that consecutive threads write consecutive addresses of a
+// digit's run.
+__global__ __launch_bounds__(256) void radix_scatter_tile(const int32_t *__restrict__ kin,
+                                                          const int32_t *__restrict__ vin,
+                                                          int64_t n, int shift,
+                                                          const int32_t *__restrict__ offs,
+                                                          int ntiles, int32_t *__restrict__ kout,
+                                                          int32_t *__restrict__ vout)
 {
-    __shared__ int32_t base[256];
-    const int lane = threadIdx.x;
-    for (int d = lane; d < 256; d += 64) base[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+    constexpr int PER = TILE / 256;           // rounds per wave (16)
+    __shared__ int32_t skey[TILE], sval[TILE];
+    __shared__ int32_t wcnt[4][256];          // digit counts per wave, then prefixes
+    __shared__ int32_t tpre[256];             // tile-local start of each digit
+    __shared__ int32_t gbase[256];            // global start of each digit (this tile)
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int d = t; d < 256; d += 256) {
+        gbase[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+        wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0;
+    }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t t0 = (int64_t)blockIdx.x * TILE;
-    for (int rnd = 0; rnd < TILE / 64; ++rnd) {
-        int64_t j = t0 + rnd * 64 + lane;
-        bool ok = j < n;
-        int32_t k = ok ? kin[j] : 0;
-        int32_t v = ok ? vin[j] : 0;
-        int dg = (k >> shift) & 255;
-        uint64_t peers = __ballot(ok);
+    const int64_t t0 = (int64_t)blockIdx.x * TILE + (int64_t)w * (TILE / 4);
+    int32_t k[PER], v[PER], dg[PER], rk[PER];
+    bool ok[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int64_t j = t0 + q * 64 + lane;
+        ok[q] = j < n;
+        k[q] = ok[q] ? kin[j] : 0;
+        v[q] = ok[q] ? vin[j] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int d = (k[q] >> shift) & 255;
+        uint64_t peers = __ballot(ok[q]);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bits = __ballot((dg >> b) & 1);
-            peers &= ((dg >> b) & 1) ? bits : ~bits;
+            const uint64_t bits = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bits : ~bits;
         }
-        int rank = __popcll(peers & lt);
-        int pos = 0;
-        if (ok) pos = base[dg] + rank;
-        __syncthreads();
-        // the highest lane of each digit group advances the running base
-        bool leader = ok && ((peers >> lane) == 1ull);
-        if (leader) base[dg] += __popcll(peers);
-        __syncthreads();
-        if (ok) {
-            kout[pos] = k;
-            vout[pos] = v;
+        dg[q] = d;
+        rk[q] = ok[q] ? wcnt[w][d] + __popcll(peers & lt) : 0;
+        // the highest lane of each digit group advances the wave's count
+        // (only this wave touches wcnt[w]; lanes of one round write
+        // different digits)
+        const bool leader = ok[q] && ((peers >> lane) == 1ull);
+        __builtin_amdgcn_wave_barrier();
+        if (leader) wcnt[w][d] += __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // prefixes: per digit over the waves, and over the digits of the tile
+    {
+        const int d = t;                      // 256 threads, one digit each
+        int c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        const int tot = c0 + c1 + c2 + c3;
+        int x = tot;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const int y = __shfl_up(x, dd);
+            if (lane >= dd) x += y;
         }
-        if (t0 + rnd * 64 + 64 >= n) break;
+        __shared__ int32_t wsum[4];
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int off = 0;
+        for (int q = 0; q < w; ++q) off += wsum[q];
+        tpre[d] = off + x - tot;
+        wcnt[0][d] = 0;
+        wcnt[1][d] = c0;
+        wcnt[2][d] = c0 + c1;
+        wcnt[3][d] = c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (ok[q]) {
+            const int pos = tpre[dg[q]] + wcnt[w][dg[q]] + rk[q];
+            skey[pos] = k[q];
+            sval[pos] = v[q];
+        }
+    __syncthreads();
+    const int64_t left = n - (int64_t)blockIdx.x * TILE;
+    const int cnt = left < TILE ? (int)left : TILE;
+    for (int p = t; p < cnt; p += 256) {
+        const int32_t key = skey[p];
+        const int d = (key >> shift) & 255;
+        const int64_t g = (int64_t)gbase[d] + (p - tpre[d]);
+        kout[g] = key;
+        vout[g] = sval[p];
     }
 }
 
