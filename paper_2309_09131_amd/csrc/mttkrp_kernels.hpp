@@ -149,6 +149,40 @@ __device__ __forceinline__ bool lane_active(int sub, int R)
     else return sub * V < R;
 }
 
+// A lane's piece of a factor row as raw 32-bit words (contiguous lane forms):
+// RW = V * sizeof(FT) / 4 words, loaded as 16-byte vectors, and its
+// conversion to V floats (FP32: the words themselves; BF16: two values per
+// word, low half first, as in Fetch).
+template <typename FT, int V>
+struct RawRow {
+    static constexpr int RW = V * (int)sizeof(FT) / 4;
+    static_assert(RW % 4 == 0, "whole 16-byte vectors");
+    static __device__ __forceinline__ void get(const void *A, int64_t row, int R, int sub,
+                                               uint32_t (&w)[RW])
+    {
+        const uint4 *q = reinterpret_cast<const uint4 *>(
+            reinterpret_cast<const FT *>(A) + row * R + sub * V);
+#pragma unroll
+        for (int i = 0; i < RW / 4; ++i) {
+            const uint4 u = q[i];
+            w[4 * i] = u.x; w[4 * i + 1] = u.y; w[4 * i + 2] = u.z; w[4 * i + 3] = u.w;
+        }
+    }
+    static __device__ __forceinline__ void unpack(const uint32_t (&w)[RW], float (&x)[V])
+    {
+        if constexpr (sizeof(FT) == 4) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) x[j] = __uint_as_float(w[j]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+                x[2 * i] = bf16lo(w[i]);
+                x[2 * i + 1] = bf16hi(w[i]);
+            }
+        }
+    }
+};
+
 // The N-1 input modes of output mode n in the layout's key order
 // n-1, n-2, ..., n+1 (cyclic, uniform).  Input 0 is the layout's second
 // key: inside an output row the nonzeros are sorted by it.
@@ -260,25 +294,29 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 
     const Inputs<N> in(a, n);
     const int fsub = ract ? sub : 0;             // in-range lane for loads
-    // Row reuse for the first NR inputs (FP32 factors).  Inside an output
-    // row the nonzeros are sorted by the input-0 coordinate, then input 1,
-    // so consecutive nonzeros of a slot often need the same input-0 row
-    // (70-99% of them on Zipf-skewed tensors) and, with five or more modes,
-    // the same input-1 row (30-75%).  Such a row is loaded only when its
-    // coordinate changes and the slot uses the row it loaded last; the
+    // Row reuse for the first NR inputs (contiguous lane forms).  Inside an
+    // output row the nonzeros are sorted by the input-0 coordinate, then
+    // input 1, so consecutive nonzeros of a slot often need the same input-0
+    // row (70-99% of them on Zipf-skewed tensors) and, with five or more
+    // modes, the same input-1 row (30-75%).  Such a row is loaded only when
+    // its coordinate changes and the slot uses the row it loaded last; the
     // products are the same.  NR = 1, or 2 from five modes on (measured;
     // with four modes the registers of a second input cost more occupancy
-    // than the loads save, and with BF16 factors even the first does).
+    // than the loads save).  The kept rows are held as the raw words loaded
+    // and widened after the selection: a BF16 row then costs half the
+    // registers of an FP32 one, and no conversion waits inside the
+    // conditional load (widening there serialised the loads).
     constexpr int NR0 = N >= 5 ? 2 : 1;
-    constexpr int NR = (sizeof(FT) == 4 && N > 2) ? (N - 2 < NR0 ? N - 2 : NR0) : 0;
+    constexpr int NR = (!STRIDED && N > 2) ? (N - 2 < NR0 ? N - 2 : NR0) : 0;
     constexpr bool REUSE = NR > 0;
-    float xp[NR > 0 ? NR : 1][V];
+    constexpr int RW = STRIDED ? 1 : V * (int)sizeof(FT) / 4;
+    uint32_t xp[NR > 0 ? NR : 1][RW];
     int pc[NR > 0 ? NR : 1];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         pc[k] = -1;
 #pragma unroll
-        for (int j = 0; j < V; ++j) xp[k][j] = 0.0f;
+        for (int j = 0; j < RW; ++j) xp[k][j] = 0u;
     }
     // Records are loaded once per lane group, not once per lane: lane `sub`
     // of a slot loads records sub, sub + LANES, ... of the slot's next U
@@ -324,15 +362,15 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                     cc[k][u] = (int)rec_coord<N>(rc[u], in.mode[k]);
                     need[k][u] = ok[u] && cc[k][u] != (u == 0 ? pc[k] : cc[k][u - 1]);
                 }
-            float xr[NR][U][V];
+            uint32_t xr[NR][U][RW];
 #pragma unroll
             for (int k = 0; k < NR; ++k)
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
 #pragma unroll
-                    for (int j = 0; j < V; ++j) xr[k][u][j] = 0.0f;
+                    for (int j = 0; j < RW; ++j) xr[k][u][j] = 0u;
                     if (need[k][u])
-                        Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)cc[k][u], R, fsub, xr[k][u]);
+                        RawRow<FT, V>::get(in.fac[k], (int64_t)cc[k][u], R, fsub, xr[k][u]);
                 }
 #pragma unroll
             for (int k = 0; k < NR; ++k)
@@ -350,10 +388,11 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                     int sel = need[k][u] ? 1 : 0;
                     asm volatile("" : "+v"(sel));
 #pragma unroll
-                    for (int j = 0; j < V; ++j) {
-                        xp[k][j] = sel ? xr[k][u][j] : xp[k][j];
-                        pr[u][j] = xp[k][j] * pr[u][j];
-                    }
+                    for (int j = 0; j < RW; ++j) xp[k][j] = sel ? xr[k][u][j] : xp[k][j];
+                    float x[V];
+                    RawRow<FT, V>::unpack(xp[k], x);
+#pragma unroll
+                    for (int j = 0; j < V; ++j) pr[u][j] = x[j] * pr[u][j];
                 }
             }
         } else {
