@@ -300,13 +300,14 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     // row (70-99% of them on Zipf-skewed tensors) and, with five or more
     // modes, the same input-1 row (30-75%).  Such a row is loaded only when
     // its coordinate changes and the slot uses the row it loaded last; the
-    // products are the same.  NR = 1, or 2 from five modes on (measured;
-    // with four modes the registers of a second input cost more occupancy
-    // than the loads save).  The kept rows are held as the raw words loaded
+    // products are the same.  NR = 1, or 2 from five modes on, and from
+    // four modes on with BF16 factors (measured; with four modes and FP32
+    // factors the registers of a second input cost more occupancy than the
+    // loads save).  The kept rows are held as the raw words loaded
     // and widened after the selection: a BF16 row then costs half the
     // registers of an FP32 one, and no conversion waits inside the
     // conditional load (widening there serialised the loads).
-    constexpr int NR0 = N >= 5 ? 2 : 1;
+    constexpr int NR0 = (N >= 5 || (N == 4 && sizeof(FT) == 2)) ? 2 : 1;
     constexpr int NR = (!STRIDED && N > 2) ? (N - 2 < NR0 ? N - 2 : NR0) : 0;
     constexpr bool REUSE = NR > 0;
     constexpr int RW = STRIDED ? 1 : V * (int)sizeof(FT) / 4;
