@@ -45,6 +45,9 @@ def log(*a):
 
 # ---------------------------------------------------------------- byte models
 def rec_bytes(N):
+    """Bytes of one COO element in the paper's traffic model: N int32
+    coordinates and the FP32 value.  (The stored records pack the
+    coordinates and can be smaller; the kernels' own figures use those.)"""
     return 4 * N + 4
 
 
@@ -61,16 +64,19 @@ def b_alg_mttkrp_kernel(dims, nnz, R, n, sf):
     return nnz * rec_bytes(N) + nnz * (N - 1) * R * sf + dims[n] * R * 4
 
 
-def b_alg_remap_kernel(dims, nnz):
-    """Record read + remap-target read + record write."""
-    return nnz * (2 * rec_bytes(len(dims)) + 4)
+def b_alg_remap_kernel(dims, nnz, rb=None):
+    """Record read + remap-target read + record write, for stored records
+    of rb bytes (default: the paper's element size)."""
+    rb = rec_bytes(len(dims)) if rb is None else rb
+    return nnz * (2 * rb + 4)
 
 
-def b_min_mttkrp_kernel(dims, nnz, R, n, sf):
-    """Compulsory bytes: every record once, every input factor once, output."""
+def b_min_mttkrp_kernel(dims, nnz, R, n, sf, rb=None):
+    """Compulsory bytes: every stored record once, every input factor once,
+    the output."""
     N = len(dims)
-    return nnz * rec_bytes(N) + sum(dims[w] * R * sf for w in range(N) if w != n) \
-        + dims[n] * R * 4
+    rb = rec_bytes(N) if rb is None else rb
+    return nnz * rb + sum(dims[w] * R * sf for w in range(N) if w != n) + dims[n] * R * 4
 
 
 def host_cpu():
@@ -240,8 +246,9 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
             nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
 
     mk_ms, mk_bytes, mk_gbs = kstats(per_mode, lambda n: b_alg_mttkrp_kernel(dims, nnz, R, n, 4))
-    rm_ms, rm_bytes, rm_gbs = kstats(per_remap, lambda n: b_alg_remap_kernel(dims, nnz))
-    mk_min = sum(b_min_mttkrp_kernel(dims, nnz, R, n, 4) for n in range(N)) / N
+    rb = plan.info(_abi.INFO_RECORD_BYTES)       # stored record bytes
+    rm_ms, rm_bytes, rm_gbs = kstats(per_remap, lambda n: b_alg_remap_kernel(dims, nnz, rb))
+    mk_min = sum(b_min_mttkrp_kernel(dims, nnz, R, n, 4, rb) for n in range(N)) / N
     ctr = os.path.join(ROOT, "profiles", f"mttkrp_kernel_{w.name}_counters.txt")
     fetch = counter_traffic(ctr, "fetch_bytes_per_launch")
     write = counter_traffic(ctr, "write_bytes_per_launch")
@@ -286,6 +293,13 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         fused_ms = timer(lambda: fplan.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
         del fplan
         log(f"fused-remap fp32 sweep {fused_ms:.3f} ms")
+    unpacked_ms = None
+    if not args.no_ablation:
+        # one 32-bit word per coordinate in the stored records
+        uplan = Plan(idx, vals, dims, R, g=args.g, flags=flags | _abi.UNPACKED_RECORDS)
+        unpacked_ms = timer(lambda: uplan.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
+        del uplan
+        log(f"unpacked-record fp32 sweep {unpacked_ms:.3f} ms")
 
     als = None
     if args.config in (1, 5):
@@ -384,7 +398,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                      if traffic else None,
                      "note": "algorithmic bytes count every gathered factor row "
                              "(paper's traffic model); most gathers hit L2/MALL"},
-        "remap_kernel": {"ms_per_launch": round(rm_ms, 4),
+        "remap_kernel": {"ms_per_launch": round(rm_ms, 4), "record_bytes": rb,
                          "alg_bytes_per_launch": int(rm_bytes),
                          "achieved_GBs": round(rm_gbs, 1),
                          "frac": round(rm_gbs / HBM_PEAK_GBS, 4)},
@@ -395,6 +409,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "fp32_error_vs_fp64_oracle": err32,
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
+        "unpacked_records_sweep_ms": round(unpacked_ms, 4) if unpacked_ms else None,
         "layout_copy_per_mode_sweep_ms": round(ncopy_ms, 4),
         "cp_als": als,
         "sweep_ms_median": round(step_ms[len(step_ms) // 2], 4),

@@ -71,6 +71,10 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
                                         kernel (the paper's same-agent remap)
                                         instead of a remap kernel right after
                                         it (default: measured faster here)  */
+#define MTTKRP_UNPACKED_RECORDS 8u   /* one 32-bit word per coordinate in the
+                                        stored records instead of the default
+                                        bit-packed form (see the workspace
+                                        description); for comparison       */
 
 /* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
 typedef struct {
@@ -99,6 +103,11 @@ mttkrp_status mttkrp_plan_workspace(int nmodes, const int64_t *dims, int64_t nnz
  * target P_n (slot of each L_n element in L_{n+1}), row pointers, the
  * super-shard / shard tables and the longest-first schedule (Alg.
  * "ss_scheduling").  The inputs are copied; they may be freed afterwards.
+ * A stored nonzero record holds its N coordinates bit-packed (b_n = bit
+ * length of I_n - 1 bits each, in mode order, in as few 32-bit words as
+ * the compiled widths allow: at least N-1 words, N-2 from five modes on)
+ * followed by the FP32 value; MTTKRP_UNPACKED_RECORDS stores one word per
+ * coordinate.  Every layout and remap moves these records unchanged.
  * The workspace must stay allocated and untouched while the plan lives.
  * Synchronous: returns after the device work finished.  ERANGE if a
  * coordinate is out of range (nothing else is then valid).
@@ -194,7 +203,8 @@ mttkrp_status cp_als(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
 
 /* Device-side plan arrays, copied into caller memory (for parity tests). */
 enum {
-    MTTKRP_Q_LAYOUT = 0,   /* current element buffer: nnz x (N int32 + f32) */
+    MTTKRP_Q_LAYOUT = 0,   /* current element buffer, widened to
+                              nnz x (N int32 + f32)                          */
     MTTKRP_Q_PERM = 1,     /* P_mode: nnz int32                              */
     MTTKRP_Q_ROW_PTR = 2,  /* I_mode + 1 int32                               */
     MTTKRP_Q_SHARDS = 3,   /* nshards x {start, len, super-shard} int32      */
@@ -202,7 +212,8 @@ enum {
 };
 /* Copies the array `what` of `mode` into dst (device or host memory,
  * hipMemcpyDefault; synchronises `stream`).  Sizes in bytes: LAYOUT
- * nnz*(N+1)*4 (the layout the tensor is currently in), PERM nnz*4, ROW_PTR
+ * nnz*(N+1)*4 (the layout the tensor is currently in, its bit-packed
+ * records widened to one int32 per coordinate on the host), PERM nnz*4, ROW_PTR
  * (I_mode+1)*4, SHARDS nshards*12, LPT k_mode*4.  EINVAL if bytes is
  * smaller. */
 mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst,
@@ -217,8 +228,9 @@ enum {
     MTTKRP_INFO_NSPLIT = 4,       /* rows of `mode` split across shards      */
     MTTKRP_INFO_G = 5,            /* shard size used                         */
     MTTKRP_INFO_M = 6,            /* super-shard size of `mode`              */
-    MTTKRP_INFO_RIDGE = 7         /* ridge count of the last cp_als_sweep
+    MTTKRP_INFO_RIDGE = 7,        /* ridge count of the last cp_als_sweep
                                      (reads device memory; synchronises)    */
+    MTTKRP_INFO_RECORD_BYTES = 8  /* bytes of one stored nonzero record     */
 };
 mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *value);
 

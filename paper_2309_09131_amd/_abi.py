@@ -20,10 +20,12 @@ F32, BF16 = 0, 1
 NO_IMPLICIT_REMAP = 1
 NATURAL_ORDER = 2
 FUSED_REMAP = 4
+UNPACKED_RECORDS = 8
 PROF_MTTKRP, PROF_REMAP, PROF_RESID, PROF_LOSS = 0, 1, 2, 3
 Q_LAYOUT, Q_PERM, Q_ROW_PTR, Q_SHARDS, Q_LPT = range(5)
 INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2
 INFO_NSPLIT, INFO_G, INFO_M, INFO_RIDGE = 4, 5, 6, 7
+INFO_RECORD_BYTES = 8
 
 SYMBOLS = ["mttkrp_plan_workspace", "mttkrp_plan", "mttkrp_mode",
            "mttkrp_all_modes", "remap", "cp_loss_grad", "cp_als_sweep", "cp_als",

@@ -6,55 +6,76 @@
 
 #define WAVE 64
 
-// One nonzero: N int32 coordinates followed by the FP32 value (4N+4 bytes).
-// Packed with 4-byte alignment; gfx950 global loads/stores of 16 bytes only
-// need dword alignment, so the compiler emits dwordx4 (+dword/dwordx2).
-template <int N>
+// One nonzero: W words holding the N coordinates bit-packed, followed by
+// the FP32 value (4W + 4 bytes).  Coordinate n occupies bits [off_n,
+// off_n + b_n) of the W words read as one little-endian bit string, b_n
+// being the bit length of I_n - 1; a coordinate may straddle two words.
+// Records are 4-byte aligned; gfx950 global loads/stores of 8 or 16 bytes
+// only need dword alignment, so the compiler emits wide accesses.
+template <int W>
 struct Rec {
-    uint32_t w[N + 1];
+    uint32_t w[W + 1];
 };
 
-template <int N>
-__device__ __forceinline__ Rec<N> load_rec(const uint32_t *__restrict__ buf, int64_t i)
+template <int W>
+__device__ __forceinline__ Rec<W> load_rec(const uint32_t *__restrict__ buf, int64_t i)
 {
     // word by word: keeps the record in registers (a struct copy through a
     // reinterpreted pointer made the compiler stage record arrays in LDS);
     // adjacent dwords are still merged into wide loads
-    Rec<N> r;
-    const uint32_t *p = buf + i * (N + 1);
+    Rec<W> r;
+    const uint32_t *p = buf + i * (W + 1);
 #pragma unroll
-    for (int k = 0; k < N + 1; ++k) r.w[k] = p[k];
+    for (int k = 0; k < W + 1; ++k) r.w[k] = p[k];
     return r;
 }
 
-template <int N>
-__device__ __forceinline__ void store_rec(uint32_t *__restrict__ buf, int64_t i, const Rec<N> &r)
+template <int W>
+__device__ __forceinline__ void store_rec(uint32_t *__restrict__ buf, int64_t i, const Rec<W> &r)
 {
-    *reinterpret_cast<Rec<N> *>(buf + i * (N + 1)) = r;
+    *reinterpret_cast<Rec<W> *>(buf + i * (W + 1)) = r;
 }
 
 // Streaming variant (non-temporal hint, per dword) for a read-once record stream.
-template <int N>
-__device__ __forceinline__ Rec<N> load_rec_nt(const uint32_t *__restrict__ buf, int64_t i)
+template <int W>
+__device__ __forceinline__ Rec<W> load_rec_nt(const uint32_t *__restrict__ buf, int64_t i)
 {
-    Rec<N> r;
-    const uint32_t *p = buf + i * (N + 1);
+    Rec<W> r;
+    const uint32_t *p = buf + i * (W + 1);
 #pragma unroll
-    for (int k = 0; k < N + 1; ++k) r.w[k] = __builtin_nontemporal_load(p + k);
+    for (int k = 0; k < W + 1; ++k) r.w[k] = __builtin_nontemporal_load(p + k);
     return r;
 }
 
-// Coordinate `n` (runtime) of a record without dynamic register indexing,
-// which would push the record to scratch memory.
-template <int N>
-__device__ __forceinline__ int rec_coord(const Rec<N> &r, int n)
+// The coordinate at bit offset `off` (runtime, uniform) with mask `mask`
+// (2^b - 1) of a record, without dynamic register indexing, which would push
+// the record to scratch memory.  The two words that can hold it are picked
+// with masks (a select chain over loaded words gets folded into a select of
+// addresses, which forces the record into memory); the second may be the
+// value word, whose bits the mask removes.
+template <int W>
+__device__ __forceinline__ int rec_coord(const Rec<W> &r, uint32_t off, uint32_t mask)
 {
-    // masks instead of selects: a select chain over loaded words gets folded
-    // into a select of addresses, which forces the record into memory
-    uint32_t v = 0;
+    const uint32_t q = off >> 5;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) v |= r.w[k] & (0u - (uint32_t)(n == k));
-    return (int)v;
+    for (int k = 0; k < W; ++k) {
+        const uint32_t m = 0u - (uint32_t)(q == (uint32_t)k);
+        lo |= r.w[k] & m;
+        hi |= r.w[k + 1] & m;
+    }
+    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    return (int)((uint32_t)(x >> (off & 31u)) & mask);
+}
+
+// The same coordinate read straight from record i of a buffer.
+template <int W>
+__device__ __forceinline__ int rec_coord_at(const uint32_t *__restrict__ buf, int64_t i,
+                                            uint32_t off, uint32_t mask)
+{
+    const uint32_t *p = buf + i * (W + 1) + (off >> 5);
+    const uint64_t x = ((uint64_t)p[1] << 32) | p[0];
+    return (int)((uint32_t)(x >> (off & 31u)) & mask);
 }
 
 // bfloat16 storage <-> float.  Widening is exact (the 16 high bits).

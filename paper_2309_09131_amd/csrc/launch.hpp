@@ -17,13 +17,24 @@ struct Args {
     int32_t nshards;
     int32_t mode;
     int32_t R;
-    int32_t pad_;
+    int32_t cw;               // coordinate words per record (W)
     const void *fac[8];       // factor matrices (I_w x R row-major)
     float *out;               // I_n x R
     float *carry;             // [nshards][2][R] boundary partials
     const double *gscale;     // residual variant: upstream scale or nullptr
     double *partial;          // loss forward: one double per shard
+    uint32_t coff[8];         // bit offset of each mode's coordinate in a record
+    uint32_t cmask[8];        // its mask, 2^b - 1
 };
+
+// Record widths compiled for N modes: W coordinate words with
+// rec_wmin(N) <= W <= N (the host rounds the packed width up into this
+// range).  W = N holds any coordinates; the narrower forms cover the
+// common case of coordinates well below 2^31.
+__host__ __device__ constexpr int rec_wmin(int N)
+{
+    return N >= 5 ? N - 2 : (N >= 2 ? N - 1 : 1);
+}
 
 // Waves (one shard each) per workgroup of the MTTKRP kernels (1, 2 and 4
 // measured equal; 8 and 12 slower).
@@ -45,20 +56,24 @@ hipError_t launch_mttkrp(const Args &a, int bf16, LaneCfg c, int kind, unsigned 
                          hipStream_t s);
 template <int N>
 hipError_t launch_remap(const uint32_t *rin, uint32_t *rout, const int32_t *perm, int64_t nnz,
-                        hipStream_t s);
+                        int cw, hipStream_t s);
+// Bit offsets of the coordinates in a packed record.
+struct PackMap {
+    uint32_t off[8];
+};
 template <int N>
 hipError_t launch_pack(const int32_t *idx, const float *vals, const int32_t *o, int64_t nnz,
-                       uint32_t *rec, hipStream_t s);
+                       uint32_t *rec, int cw, PackMap pm, hipStream_t s);
 
 #define MK_DECLARE(N)                                                                      \
     template <>                                                                            \
     hipError_t launch_mttkrp<N>(const Args &, int, LaneCfg, int, unsigned, hipStream_t);   \
     template <>                                                                            \
     hipError_t launch_remap<N>(const uint32_t *, uint32_t *, const int32_t *, int64_t,     \
-                               hipStream_t);                                               \
+                               int, hipStream_t);                                          \
     template <>                                                                            \
     hipError_t launch_pack<N>(const int32_t *, const float *, const int32_t *, int64_t,    \
-                              uint32_t *, hipStream_t);
+                              uint32_t *, int, PackMap, hipStream_t);
 MK_DECLARE(2)
 MK_DECLARE(3)
 MK_DECLARE(4)

@@ -189,14 +189,15 @@ struct RawRow {
 template <int N>
 struct Inputs {
     const void *fac[N > 1 ? N - 1 : 1];
-    int mode[N > 1 ? N - 1 : 1];
+    uint32_t off[N > 1 ? N - 1 : 1], msk[N > 1 ? N - 1 : 1];   // coordinate in a record
     __device__ __forceinline__ Inputs(const Args &a, int n)
     {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) {
             const int w = (n + N - 1 - k) % N;
-            mode[k] = w;
             fac[k] = a.fac[w];
+            off[k] = a.coff[w];
+            msk[k] = a.cmask[w];
         }
     }
 };
@@ -205,8 +206,8 @@ struct Inputs {
 // there are none).  Every load is unconditional (the caller passes an
 // in-range record and lane), so the compiler can keep all gathers of an
 // unrolled group in flight at once.
-template <int N, typename FT, int V, bool STRIDED, int K0>
-__device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<N> &rc, int R,
+template <int N, int W, typename FT, int V, bool STRIDED, int K0>
+__device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<W> &rc, int R,
                                             int sub, float (&pr)[V])
 {
 #pragma unroll
@@ -214,15 +215,16 @@ __device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<N> &r
 #pragma unroll
     for (int k = K0; k < N - 1; ++k) {
         float x[V];
-        Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)rec_coord<N>(rc, in.mode[k]), R, sub, x);
+        Fetch<FT, V, STRIDED>::get(in.fac[k], (int64_t)rec_coord<W>(rc, in.off[k], in.msk[k]), R,
+                                   sub, x);
 #pragma unroll
         for (int j = 0; j < V; ++j) pr[j] *= x[j];
     }
 }
 
 // Product over all N modes (loss forward).
-template <int N, typename FT, int V, bool STRIDED>
-__device__ __forceinline__ void row_product_all(const Args &a, const Rec<N> &rc, int R, int sub,
+template <int N, int W, typename FT, int V, bool STRIDED>
+__device__ __forceinline__ void row_product_all(const Args &a, const Rec<W> &rc, int R, int sub,
                                                 float (&pr)[V])
 {
 #pragma unroll
@@ -230,7 +232,8 @@ __device__ __forceinline__ void row_product_all(const Args &a, const Rec<N> &rc,
 #pragma unroll
     for (int w = 0; w < N; ++w) {
         float x[V];
-        Fetch<FT, V, STRIDED>::get(a.fac[w], (int64_t)rc.w[w], R, sub, x);
+        Fetch<FT, V, STRIDED>::get(a.fac[w], (int64_t)rec_coord<W>(rc, a.coff[w], a.cmask[w]), R,
+                                   sub, x);
 #pragma unroll
         for (int j = 0; j < V; ++j) pr[j] *= x[j];
     }
@@ -252,7 +255,7 @@ __device__ __forceinline__ float slot_sum(float v)
 // a row that starts and ends inside the run is complete and written at
 // once.  The first row of each run (head) and the last (tail) are then
 // joined across slots with one segmented scan per shard.
-template <int N, typename FT, int LANES, int V, bool STRIDED, bool RESID, bool FUSE>
+template <int N, int W, typename FT, int LANES, int V, bool STRIDED, bool RESID, bool FUSE>
 __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
@@ -269,8 +272,9 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     const int n = a.mode, R = a.R;
     const int slot = lane / LANES, sub = lane % LANES;
     const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
-    const int f = (int)a.rin[(int64_t)start * (N + 1) + n];
-    const int l = (int)a.rin[(int64_t)(end - 1) * (N + 1) + n];
+    const uint32_t noff = a.coff[n], nmsk = a.cmask[n];     // output coordinate
+    const int f = rec_coord_at<W>(a.rin, start, noff, nmsk);
+    const int l = rec_coord_at<W>(a.rin, end - 1, noff, nmsk);
     const bool split_before = a.row_ptr[f] < start;
     float coef = 1.0f;
     if constexpr (RESID) coef = -2.0f * (a.gscale ? (float)a.gscale[0] : 1.0f);
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     const int run = (len + SW - 1) / SW;
     const int s0 = start + slot * run;
     const int s1 = min(s0 + run, end);           // s0 >= s1: empty run (row l)
-    int cur_row = (s0 < s1) ? (int)a.rin[(int64_t)s0 * (N + 1) + n] : l;
+    int cur_row = (s0 < s1) ? rec_coord_at<W>(a.rin, s0, noff, nmsk) : l;
     const int head_row = cur_row;
     bool in_head = true;
     float acc[V], head[V];
@@ -326,15 +330,15 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     // per CU) limits this kernel, so duplicate loads are expensive.  The
     // next group's records are loaded while the current group computes.
     constexpr int RPL = (U + LANES - 1) / LANES;
-    Rec<N> nxt[RPL];
+    Rec<W> nxt[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; ++j) {
         const int u = sub + j * LANES;
         const int e = s0 + u;
-        nxt[j] = load_rec<N>(a.rin, (u < U && u < run && e < end) ? e : start);
+        nxt[j] = load_rec<W>(a.rin, (u < U && u < run && e < end) ? e : start);
     }
     for (int k = 0; k < run; k += U) {           // uniform trip count
-        Rec<N> rc[U];
+        Rec<W> rc[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -342,14 +346,14 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             ok[u] = (k + u < run) && (e < end);
             const int src = slot * LANES + (u % LANES);
 #pragma unroll
-            for (int w = 0; w < N + 1; ++w)
+            for (int w = 0; w < W + 1; ++w)
                 rc[u].w[w] = (uint32_t)__shfl((int)nxt[u / LANES].w[w], src);
         }
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {            // clamped index: no branch
             const int u = sub + j * LANES;
             const int e = s0 + k + U + u;
-            nxt[j] = load_rec<N>(a.rin, (u < U && k + U + u < run && e < end) ? e : start);
+            nxt[j] = load_rec<W>(a.rin, (u < U && k + U + u < run && e < end) ? e : start);
         }
         float pr[U][V];
         float mm[U];
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             for (int k = 0; k < NR; ++k)
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    cc[k][u] = (int)rec_coord<N>(rc[u], in.mode[k]);
+                    cc[k][u] = rec_coord<W>(rc[u], in.off[k], in.msk[k]);
                     need[k][u] = ok[u] && cc[k][u] != (u == 0 ? pc[k] : cc[k][u - 1]);
                 }
             uint32_t xr[NR][U][RW];
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                     if (ok[u]) pc[k] = cc[k][u];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                row_product<N, FT, V, STRIDED, NR>(in, rc[u], R, fsub, pr[u]);
+                row_product<N, W, FT, V, STRIDED, NR>(in, rc[u], R, fsub, pr[u]);
 #pragma unroll
                 for (int k = NR - 1; k >= 0; --k) {
                     // opaque copy of the flag: keeps the compiler from
@@ -398,14 +402,16 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             }
         } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u) row_product<N, FT, V, STRIDED, 0>(in, rc[u], R, fsub, pr[u]);
+            for (int u = 0; u < U; ++u)
+                row_product<N, W, FT, V, STRIDED, 0>(in, rc[u], R, fsub, pr[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             mm[u] = 0.0f;
             if constexpr (RESID) {
                 float xn[V];
-                Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)rec_coord<N>(rc[u], n), R, fsub, xn);
+                Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)rec_coord<W>(rc[u], noff, nmsk), R,
+                                           fsub, xn);
 #pragma unroll
                 for (int j = 0; j < V; ++j) mm[u] += pr[u][j] * xn[j];
                 if (!(ok[u] && ract)) mm[u] = 0.0f;
@@ -417,7 +423,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             for (int u = 0; u < U; ++u) dst[u] = a.perm[ok[u] ? s0 + k + u : start];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u] && sub == 0) store_rec<N>(a.rout, dst[u], rc[u]);
+                if (ok[u] && sub == 0) store_rec<W>(a.rout, dst[u], rc[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -425,12 +431,12 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             if constexpr (RESID) {
                 // model value m_e (lanes outside the rank range hold 0)
                 const float m = slot_sum<LANES>(mm[u]);
-                if (ok[u]) c = coef * (__uint_as_float(rc[u].w[N]) - m);
+                if (ok[u]) c = coef * (__uint_as_float(rc[u].w[W]) - m);
             } else {
-                if (ok[u]) c = __uint_as_float(rc[u].w[N]);
+                if (ok[u]) c = __uint_as_float(rc[u].w[W]);
             }
             if (ok[u]) {
-                const int row = (int)rec_coord<N>(rc[u], n);
+                const int row = rec_coord<W>(rc[u], noff, nmsk);
                 if (row != cur_row) {
                     if (in_head) {
 #pragma unroll
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 }
 
 // ---- sampled CP loss forward: one double partial per shard ---------------
-template <int N, typename FT, int LANES, int V, bool STRIDED>
+template <int N, int W, typename FT, int LANES, int V, bool STRIDED>
 __global__ __launch_bounds__(256) void loss_kernel(Args a)
 {
     constexpr int SW = WAVE / LANES;
@@ -517,18 +523,18 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
     const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
     double acc = 0.0;
     for (int base = start; base < end; base += U * SW) {
-        Rec<N> rc[U];
+        Rec<W> rc[U];
         float m[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = base + u * SW + slot;
-            rc[u] = load_rec<N>(a.rin, e < end ? e : start);   // clamped, no branch
+            rc[u] = load_rec<W>(a.rin, e < end ? e : start);   // clamped, no branch
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = base + u * SW + slot;
             float pr[V];
-            row_product_all<N, FT, V, STRIDED>(a, rc[u], R, ract ? sub : 0, pr);
+            row_product_all<N, W, FT, V, STRIDED>(a, rc[u], R, ract ? sub : 0, pr);
             m[u] = 0.0f;
 #pragma unroll
             for (int j = 0; j < V; ++j) m[u] += pr[j];
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
             const int e = base + u * SW + slot;
             const float mu = slot_sum<LANES>(m[u]);
             if (e < end && sub == 0) {
-                const float rho = __uint_as_float(rc[u].w[N]) - mu;
+                const float rho = __uint_as_float(rc[u].w[W]) - mu;
                 acc += (double)(rho * rho);    // FP32 term, FP64 accumulation
             }
         }
@@ -560,25 +566,27 @@ __global__ __launch_bounds__(256) void loss_kernel(Args a)
 // Records per thread (RT): 16, fewer when the LDS stage of 256 * RT records
 // plus their targets would exceed 96 KB.  The host sizes the grid with the
 // same function.
-template <int N>
+template <int W>
 __host__ __device__ constexpr int remap_rt()
 {
     // 16 measured fastest of 8, 12, 16, 24 and 30
     constexpr int RT0 = 16;
-    constexpr int RTC = (96 * 1024) / (256 * (4 * (N + 1) + 4));
+    constexpr int RTC = (96 * 1024) / (256 * (4 * (W + 1) + 4));
     return RT0 < RTC ? RT0 : RTC;
 }
 
-template <int N>
+// (TU, the mode count of the translation unit, only keeps the symbol of
+// each instantiation unique to one code object.)
+template <int TU, int W>
 __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__ rin,
                                                     uint32_t *__restrict__ rout,
                                                     const int32_t *__restrict__ perm,
                                                     int64_t nnz)
 {
-    constexpr int RT = remap_rt<N>();
+    constexpr int RT = remap_rt<W>();
     constexpr int RB = 256 * RT;
     constexpr int NB = 1024;              // buckets
-    __shared__ Rec<N> srec[RB];
+    __shared__ Rec<W> srec[RB];
     __shared__ int32_t sdst[RB];
     __shared__ int32_t cnt[NB];
     const int t = threadIdx.x;
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
         const int64_t base = chunk * RB;
         for (int k = t; k < NB; k += 256) cnt[k] = 0;
         __syncthreads();
-        Rec<N> r[RT];
+        Rec<W> r[RT];
         int32_t d[RT], pos[RT];
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
@@ -602,17 +610,19 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
             const bool ok = i < nnz;
             // Read-once streams are loaded non-temporal, so they do not
             // evict the partly written destination lines that wait in L2 for
-            // their other records.  Records only when one or two 16-byte
-            // loads cover them (3 and 7 modes): for 20- and 24-byte records
-            // non-temporal loads measured 15-45% slower, also when the chunk
-            // was first staged so that every line is read once.
-            if constexpr ((N + 1) % 4 == 0) r[k] = load_rec_nt<N>(rin, ok ? i : 0);
-            else r[k] = load_rec<N>(rin, ok ? i : 0);
+            // their other records, nor the new layout in the Infinity Cache,
+            // which the next MTTKRP reads (12-byte records: that kernel
+            // 0.237 -> 0.215 ms).  Records only when they are 12, 16 or 32
+            // bytes: for 20- and 24-byte records non-temporal loads measured
+            // 15-45% slower, also when the chunk was first staged so that
+            // every line is read once.
+            if constexpr ((W + 1) % 4 == 0 || W + 1 == 3) r[k] = load_rec_nt<W>(rin, ok ? i : 0);
+            else r[k] = load_rec<W>(rin, ok ? i : 0);
             d[k] = ok ? __builtin_nontemporal_load(perm + i) : -1;
         }
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
-            const int b = (d[k] >= 0) ? (int)(((int64_t)d[k] * (N + 1) / 32) & (NB - 1)) : NB - 1;
+            const int b = (d[k] >= 0) ? (int)(((int64_t)d[k] * (W + 1) / 32) & (NB - 1)) : NB - 1;
             pos[k] = atomicAdd(&cnt[b], 1);   // LDS atomic: slot within bucket
             d[k] = (d[k] >= 0) ? d[k] : -1;
             pos[k] |= b << 16;
@@ -652,7 +662,7 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
         for (int k = 0; k < RT; ++k) {
             const int slot = k * 256 + t;
             const int32_t dst = sdst[slot];
-            if (dst >= 0) store_rec<N>(rout, dst, srec[slot]);
+            if (dst >= 0) store_rec<W>(rout, dst, srec[slot]);
         }
         __syncthreads();
     }

@@ -37,6 +37,9 @@ struct Layout {
     int g;
     int workers;
     uint32_t flags;
+    int cw;                            // coordinate words per record
+    uint32_t coff[MTTKRP_MAX_MODES];   // bit offset of each coordinate in a record
+    uint32_t cmask[MTTKRP_MAX_MODES];  // its mask
     int64_t m[MTTKRP_MAX_MODES], k[MTTKRP_MAX_MODES], maxS[MTTKRP_MAX_MODES];
     size_t off_rec[2], off_perm[MTTKRP_MAX_MODES], off_rp[MTTKRP_MAX_MODES];
     size_t off_sh[MTTKRP_MAX_MODES], off_ord[MTTKRP_MAX_MODES], off_split[MTTKRP_MAX_MODES];
@@ -87,7 +90,22 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
         L->k[n] = (dims[n] + L->m[n] - 1) / L->m[n];
         L->maxS[n] = (nnz + L->g - 1) / L->g + L->k[n];
     }
-    const int NW = N + 1;
+    // Record format: the coordinates bit-packed in mode order, b_n = bit
+    // length of I_n - 1 bits each (a coordinate may straddle two words), in
+    // cw words, rounded up to the narrowest compiled width; or one word per
+    // coordinate when the plan asks for it.  A 0-bit coordinate (I_n = 1)
+    // sits at offset 0 with an empty mask.
+    const bool unpacked = (L->flags & MTTKRP_UNPACKED_RECORDS) != 0;
+    int tot = 0;
+    for (int n = 0; n < N; ++n) {
+        int b = 0;
+        while ((int64_t(1) << b) < dims[n]) ++b;
+        L->coff[n] = unpacked ? 32u * n : (b ? (uint32_t)tot : 0u);
+        L->cmask[n] = b ? (uint32_t)((uint64_t(1) << b) - 1) : 0u;
+        tot += b;
+    }
+    L->cw = unpacked ? N : std::max(mk::rec_wmin(N), (tot + 31) / 32);
+    const int NW = L->cw + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L->off_rec[0] = take((size_t)nnz * NW * 4);
@@ -235,32 +253,35 @@ static hipError_t launch_mttkrp_any(int N, const mk::Args &a, int bf16, mk::Lane
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_remap_any(int N, const uint32_t *rin, uint32_t *rout,
+static hipError_t launch_remap_any(int N, int cw, const uint32_t *rin, uint32_t *rout,
                                    const int32_t *perm, int64_t nnz, hipStream_t s)
 {
     switch (N) {
-    case 2: return mk::launch_remap<2>(rin, rout, perm, nnz, s);
-    case 3: return mk::launch_remap<3>(rin, rout, perm, nnz, s);
-    case 4: return mk::launch_remap<4>(rin, rout, perm, nnz, s);
-    case 5: return mk::launch_remap<5>(rin, rout, perm, nnz, s);
-    case 6: return mk::launch_remap<6>(rin, rout, perm, nnz, s);
-    case 7: return mk::launch_remap<7>(rin, rout, perm, nnz, s);
-    case 8: return mk::launch_remap<8>(rin, rout, perm, nnz, s);
+    case 2: return mk::launch_remap<2>(rin, rout, perm, nnz, cw, s);
+    case 3: return mk::launch_remap<3>(rin, rout, perm, nnz, cw, s);
+    case 4: return mk::launch_remap<4>(rin, rout, perm, nnz, cw, s);
+    case 5: return mk::launch_remap<5>(rin, rout, perm, nnz, cw, s);
+    case 6: return mk::launch_remap<6>(rin, rout, perm, nnz, cw, s);
+    case 7: return mk::launch_remap<7>(rin, rout, perm, nnz, cw, s);
+    case 8: return mk::launch_remap<8>(rin, rout, perm, nnz, cw, s);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_pack_any(int N, const int32_t *idx, const float *vals, const int32_t *o,
-                                  int64_t nnz, uint32_t *rec, hipStream_t s)
+static hipError_t launch_pack_any(const Layout &L, const int32_t *idx, const float *vals,
+                                  const int32_t *o, uint32_t *rec, hipStream_t s)
 {
-    switch (N) {
-    case 2: return mk::launch_pack<2>(idx, vals, o, nnz, rec, s);
-    case 3: return mk::launch_pack<3>(idx, vals, o, nnz, rec, s);
-    case 4: return mk::launch_pack<4>(idx, vals, o, nnz, rec, s);
-    case 5: return mk::launch_pack<5>(idx, vals, o, nnz, rec, s);
-    case 6: return mk::launch_pack<6>(idx, vals, o, nnz, rec, s);
-    case 7: return mk::launch_pack<7>(idx, vals, o, nnz, rec, s);
-    case 8: return mk::launch_pack<8>(idx, vals, o, nnz, rec, s);
+    mk::PackMap pm;
+    for (int n = 0; n < 8; ++n) pm.off[n] = n < L.N ? L.coff[n] : 0u;
+    const int64_t nnz = L.nnz;
+    switch (L.N) {
+    case 2: return mk::launch_pack<2>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 3: return mk::launch_pack<3>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 4: return mk::launch_pack<4>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 5: return mk::launch_pack<5>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 6: return mk::launch_pack<6>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 7: return mk::launch_pack<7>(idx, vals, o, nnz, rec, L.cw, pm, s);
+    case 8: return mk::launch_pack<8>(idx, vals, o, nnz, rec, L.cw, pm, s);
     }
     return hipErrorInvalidValue;
 }
@@ -595,7 +616,8 @@ static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
         ev.b = take_event(p);
         if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
     }
-    HIPCHK(p, launch_remap_any(L.N, p->rec(p->buf), p->rec(p->buf ^ 1), p->perm(p->cur), L.nnz, s));
+    HIPCHK(p, launch_remap_any(L.N, L.cw, p->rec(p->buf), p->rec(p->buf ^ 1), p->perm(p->cur),
+                               L.nnz, s));
     if (p->prof) {
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);
@@ -671,7 +693,12 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.nshards = (int32_t)p->nshards[n];
     a.mode = n;
     a.R = L.R;
-    for (int w = 0; w < L.N; ++w) a.fac[w] = facs[w];
+    a.cw = L.cw;
+    for (int w = 0; w < L.N; ++w) {
+        a.fac[w] = facs[w];
+        a.coff[w] = L.coff[w];
+        a.cmask[w] = L.cmask[w];
+    }
     a.out = out;
     const int cs = p->carry_sel;
     a.carry = p->rt<float>(L.rt_carry[cs]);
@@ -848,7 +875,7 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
             return bail(fail(p, MTTKRP_EHIP, "copy"));
         src = ob[0];
     }
-    if (launch_pack_any(N, d_idx, d_vals, ob[0], nnz, p->rec(0), s) != hipSuccess)
+    if (launch_pack_any(L, d_idx, d_vals, ob[0], p->rec(0), s) != hipSuccess)
         return bail(fail(p, MTTKRP_EHIP, "pack launch"));
     // 3. per mode: row pointers of L_n; P_n by a stable sort of L_n by c_{n+1}
     int oc = 0;
@@ -875,8 +902,8 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
         double *part = p->rt<double>(L.rt_partial);   // sort buffers are free now
         if (hipStreamSynchronize(s) != hipSuccess)
             return bail(fail(p, MTTKRP_EHIP, "plan sync"));
-        hipLaunchKernelGGL(als::sumsq_partial, dim3(nb), dim3(256), 0, s, p->rec(0), nnz, N + 1,
-                           part);
+        hipLaunchKernelGGL(als::sumsq_partial, dim3(nb), dim3(256), 0, s, p->rec(0), nnz,
+                           L.cw + 1, part);
         hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)nb, p->xx());
     }
     // 4. host partition tables
@@ -1179,6 +1206,26 @@ mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst, 
     }
     if (!dst || bytes < (size_t)need) return fail(p, MTTKRP_EINVAL, "destination too small");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (what == MTTKRP_Q_LAYOUT && need > 0) {
+        // stored records are bit-packed: widen to N coordinates + value
+        const int NW = L.cw + 1, N = L.N;
+        std::vector<uint32_t> packed((size_t)L.nnz * NW), wide((size_t)L.nnz * (N + 1));
+        HIPCHK(p, hipMemcpyAsync(packed.data(), src, packed.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        for (int64_t i = 0; i < L.nnz; ++i) {
+            const uint32_t *r = packed.data() + i * NW;
+            uint32_t *o = wide.data() + i * (N + 1);
+            for (int n = 0; n < N; ++n) {
+                const uint32_t q = L.coff[n] >> 5;
+                const uint64_t x = ((uint64_t)r[q + 1] << 32) | r[q];
+                o[n] = (uint32_t)(x >> (L.coff[n] & 31u)) & L.cmask[n];
+            }
+            o[N] = r[NW - 1];
+        }
+        HIPCHK(p, hipMemcpyAsync(dst, wide.data(), need, hipMemcpyDefault, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        return MTTKRP_OK;
+    }
     if (need > 0) HIPCHK(p, hipMemcpyAsync(dst, src, need, hipMemcpyDefault, s));
     HIPCHK(p, hipStreamSynchronize(s));
     return MTTKRP_OK;
@@ -1191,6 +1238,7 @@ mttkrp_status mttkrp_plan_info(mttkrp_plan_t p, int what, int mode, int64_t *val
     auto mode_ok = [&]() { return mode >= 0 && mode < L.N; };
     switch (what) {
     case MTTKRP_INFO_CUR_MODE: *value = p->cur; return MTTKRP_OK;
+    case MTTKRP_INFO_RECORD_BYTES: *value = 4 * (L.cw + 1); return MTTKRP_OK;
     case MTTKRP_INFO_G: *value = L.g; return MTTKRP_OK;
     case MTTKRP_INFO_NSHARDS:
     case MTTKRP_INFO_NSUPER:

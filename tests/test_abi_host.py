@@ -81,3 +81,27 @@ def test_calls_on_null_plan_are_einval(lib):
 def test_status_strings(lib):
     for st in range(6):
         assert len(_abi.mttkrp_status_str(st)) > 0
+
+
+def _align(x):
+    return (x + 255) & ~255
+
+
+@pytest.mark.parametrize("dims, packed_words", [
+    ((50000, 40000, 30000), 2),                 # 16 + 16 + 15 bits
+    ((300000, 200000, 5000), 2),                # 19 + 18 + 13: mode 1 straddles a word
+    ((1 << 30, 1 << 30, 1 << 30), 3),           # 90 bits: no saving
+    ((70000, 90000, 5000, 300), 3),             # 56 bits, but at least N - 1 words
+    ((2000000, 1000000, 100000, 5000, 500), 3),  # 80 bits, N - 2 words from five modes
+    ((1, 5, 1), 2),                             # 0-bit modes
+])
+def test_record_width_from_dimensions(lib, dims, packed_words):
+    """The stored record is (packed coordinate words + 1) * 4 bytes; with
+    MTTKRP_UNPACKED_RECORDS it is (N + 1) * 4.  Only the two record buffers
+    of the workspace depend on it."""
+    nnz, N = 100003, len(dims)
+    packed = _abi.mttkrp_plan_workspace(N, dims, nnz, 16)
+    wide = _abi.mttkrp_plan_workspace(N, dims, nnz, 16,
+                                      _abi.make_opts(flags=_abi.UNPACKED_RECORDS))
+    rec = lambda words: _align(nnz * 4 * (words + 1))
+    assert wide - packed == 2 * (rec(N) - rec(packed_words))

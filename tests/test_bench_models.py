@@ -30,9 +30,12 @@ def test_workload2_sweep_bytes():
     k = bench.b_alg_mttkrp_kernel(dims, nnz, R, 0, 4)
     assert k == nnz * (16 + 2 * 32 * 4) + dims[0] * R * 4
     assert bench.b_alg_remap_kernel(dims, nnz) == nnz * 36
+    # stored records of 12 bytes (16 + 16 + 15 coordinate bits in two words)
+    assert bench.b_alg_remap_kernel(dims, nnz, 12) == nnz * 28
     # compulsory: records once, each input factor once, the output
     m = bench.b_min_mttkrp_kernel(dims, nnz, R, 0, 4)
     assert m == nnz * 16 + (40000 + 30000) * R * 4 + 50000 * R * 4
+    assert bench.b_min_mttkrp_kernel(dims, nnz, R, 0, 4, 12) == m - nnz * 4
 
 
 def test_counter_summary_is_used_only_for_the_profiled_sources(tmp_path):

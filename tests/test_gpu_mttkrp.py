@@ -73,6 +73,9 @@ MTT_CASES = [
     ((4, 500, 300), 20000, 16, 23, True, 1.5, 64),    # rows over many shards
     ((3, 200, 100), 150000, 8, 24, False, 0.0, 2),    # ~75K partials: 3 levels
     ((60, 50, 2, 10, 9), 20000, 16, 25, True, 0.0, 64),  # a 2-index mode
+    # packed records: 19 + 18 + 13 bits in two words, mode 1 straddling them
+    ((300000, 200000, 5000), 5000, 16, 26, True, 0.0, 64),
+    ((70000, 90000, 5000, 300), 6000, 32, 27, True, 1.1, 128),   # 17 + 17 + 13 + 9 bits
 ]
 
 
@@ -81,7 +84,7 @@ def _oracle_all(t, facs64):
             for n in range(len(t.dims))]
 
 
-@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP, _abi.UNPACKED_RECORDS])
 @pytest.mark.parametrize("case", MTT_CASES)
 def test_mttkrp_all_modes_fp32(case, flags):
     dims, nnz, R, seed, distinct, zipf, g = case
@@ -194,3 +197,24 @@ def test_one_output_buffer_for_every_mode(flags):
         torch.cuda.synchronize()
         ref, rabs = oracle.mttkrp(dims, t.idx, t.vals, t.factors, 2, with_abs=True)
         check_close(outs[2].cpu().numpy(), ref, rabs, FP32_TOL, "last mode")
+
+
+@pytest.mark.parametrize("dims, words", [((50000, 40000, 30000), 2),
+                                         ((300000, 200000, 5000), 2),
+                                         ((70000, 90000, 5000, 300), 3),
+                                         ((3, 2, 2, 3, 2, 2, 3, 2), 6)])
+def test_record_bytes_and_layout(dims, words):
+    """Stored records are (packed words + 1) * 4 bytes, (N + 1) * 4 unpacked;
+    both forms give the oracle's layout for every mode."""
+    say("record width", dims)
+    t = syn.random_tensor(dims, 3000, 8, 28, distinct=False)
+    l0 = oracle.canonical_order(t.idx)
+    layouts, _, _ = oracle.remap_replay(dims, t.idx, l0)
+    N = len(dims)
+    for flags, nbytes in ((0, 4 * (words + 1)), (_abi.UNPACKED_RECORDS, 4 * (N + 1))):
+        p, _ = make_plan(t, g=64, flags=flags)
+        assert p.info(_abi.INFO_RECORD_BYTES) == nbytes
+        for n in range(N + 1):
+            assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                                  oracle_layout_records(t, layouts[n])), (flags, n)
+            p.remap((n + 1) % N)
