@@ -48,21 +48,21 @@ __device__ __forceinline__ Rec<W> load_rec_nt(const uint32_t *__restrict__ buf, 
 }
 
 // The coordinate at bit offset `off` (runtime, uniform) with mask `mask`
-// (2^b - 1) of a record, without dynamic register indexing, which would push
-// the record to scratch memory.  The two words that can hold it are picked
-// with masks (a select chain over loaded words gets folded into a select of
-// addresses, which forces the record into memory); the second may be the
+// (2^b - 1) of a record held in registers, without dynamic register
+// indexing, which would push the record to scratch memory: the two words
+// that can hold it are picked with selects on the uniform word index (one
+// select per word and half; and-or masks measured 2-3% slower in the MTTKRP
+// kernel), then shifted as one 64-bit value.  The second word may be the
 // value word, whose bits the mask removes.
 template <int W>
 __device__ __forceinline__ int rec_coord(const Rec<W> &r, uint32_t off, uint32_t mask)
 {
     const uint32_t q = off >> 5;
-    uint32_t lo = 0, hi = 0;
+    uint32_t lo = r.w[0], hi = r.w[1];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const uint32_t m = 0u - (uint32_t)(q == (uint32_t)k);
-        lo |= r.w[k] & m;
-        hi |= r.w[k + 1] & m;
+    for (int k = 1; k < W; ++k) {
+        lo = (q == (uint32_t)k) ? r.w[k] : lo;
+        hi = (q == (uint32_t)k) ? r.w[k + 1] : hi;
     }
     const uint64_t x = ((uint64_t)hi << 32) | lo;
     return (int)((uint32_t)(x >> (off & 31u)) & mask);
