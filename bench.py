@@ -357,6 +357,21 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
             log(f"g {gk}: plan {pms:.1f} ms, sweep {mk:.3f} ms")
             del pk
         ablations["g_sweep"] = rows
+    if args.m_sweep:
+        # super-shard size m_n (Sec. III-A, V-A), the same for every mode
+        # (capped at I_n); 0 = the default rule
+        rows = []
+        for mk_ in [int(x) for x in args.m_sweep.split(",")]:
+            pk = Plan(idx, vals, dims, R, g=args.g, m=[mk_] * N if mk_ > 0 else None)
+            mk = timer(lambda: pk.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
+            rows.append({"m": mk_ if mk_ > 0 else "default",
+                         "m_used": [pk.info(_abi.INFO_M, n) for n in range(N)],
+                         "super_shards": [pk.info(_abi.INFO_NSUPER, n) for n in range(N)],
+                         "shards": [pk.info(_abi.INFO_NSHARDS, n) for n in range(N)],
+                         "sweep_ms": round(mk, 4)})
+            log(f"m {mk_}: sweep {mk:.3f} ms")
+            del pk
+        ablations["m_sweep"] = rows
 
     del idx, vals
     cpu = None
@@ -646,6 +661,8 @@ def main():
                     help="size of a plain device copy run for counter calibration")
     ap.add_argument("--rank-sweep", default="",
                     help="comma-separated ranks: sweep time against R on the same tensor")
+    ap.add_argument("--m-sweep", default="",
+                    help="comma-separated super-shard sizes m (0 = default rule)")
     ap.add_argument("--g-sweep", default="",
                     help="comma-separated shard sizes g: plan and sweep time against g")
     ap.add_argument("--als-recovery", type=int, default=0, metavar="D",
