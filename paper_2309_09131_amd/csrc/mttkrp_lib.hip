@@ -1207,23 +1207,33 @@ mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst, 
     if (!dst || bytes < (size_t)need) return fail(p, MTTKRP_EINVAL, "destination too small");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (what == MTTKRP_Q_LAYOUT && need > 0) {
-        // stored records are bit-packed: widen to N coordinates + value
+        // stored records are bit-packed: widen to N coordinates + value, in
+        // chunks so that the host buffers stay small for any nnz
         const int NW = L.cw + 1, N = L.N;
-        std::vector<uint32_t> packed((size_t)L.nnz * NW), wide((size_t)L.nnz * (N + 1));
-        HIPCHK(p, hipMemcpyAsync(packed.data(), src, packed.size() * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(p, hipStreamSynchronize(s));
-        for (int64_t i = 0; i < L.nnz; ++i) {
-            const uint32_t *r = packed.data() + i * NW;
-            uint32_t *o = wide.data() + i * (N + 1);
-            for (int n = 0; n < N; ++n) {
-                const uint32_t q = L.coff[n] >> 5;
-                const uint64_t x = ((uint64_t)r[q + 1] << 32) | r[q];
-                o[n] = (uint32_t)(x >> (L.coff[n] & 31u)) & L.cmask[n];
+        const int64_t CH = int64_t(1) << 20;
+        std::vector<uint32_t> packed((size_t)std::min(CH, L.nnz) * NW);
+        std::vector<uint32_t> wide((size_t)std::min(CH, L.nnz) * (N + 1));
+        const uint32_t *srec = static_cast<const uint32_t *>(src);
+        char *out = static_cast<char *>(dst);
+        for (int64_t c0 = 0; c0 < L.nnz; c0 += CH) {
+            const int64_t cn = std::min(CH, L.nnz - c0);
+            HIPCHK(p, hipMemcpyAsync(packed.data(), srec + c0 * NW, (size_t)cn * NW * 4,
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(p, hipStreamSynchronize(s));
+            for (int64_t i = 0; i < cn; ++i) {
+                const uint32_t *r = packed.data() + i * NW;
+                uint32_t *o = wide.data() + i * (N + 1);
+                for (int n = 0; n < N; ++n) {
+                    const uint32_t q = L.coff[n] >> 5;
+                    const uint64_t x = ((uint64_t)r[q + 1] << 32) | r[q];
+                    o[n] = (uint32_t)(x >> (L.coff[n] & 31u)) & L.cmask[n];
+                }
+                o[N] = r[NW - 1];
             }
-            o[N] = r[NW - 1];
+            HIPCHK(p, hipMemcpyAsync(out + c0 * (N + 1) * 4, wide.data(), (size_t)cn * (N + 1) * 4,
+                                     hipMemcpyDefault, s));
+            HIPCHK(p, hipStreamSynchronize(s));
         }
-        HIPCHK(p, hipMemcpyAsync(dst, wide.data(), need, hipMemcpyDefault, s));
-        HIPCHK(p, hipStreamSynchronize(s));
         return MTTKRP_OK;
     }
     if (need > 0) HIPCHK(p, hipMemcpyAsync(dst, src, need, hipMemcpyDefault, s));
