@@ -411,8 +411,11 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                      "traffic_GBs": round(traffic / (mk_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "traffic_frac": round(traffic / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                      if traffic else None,
-                     "note": "algorithmic bytes count every gathered factor row "
-                             "(paper's traffic model); most gathers hit L2/MALL"},
+                     "stored_record_bytes": rb,
+                     "note": "algorithmic bytes count every gathered factor row and "
+                             "4N+4-byte records (paper's traffic model; the stored "
+                             "records are bit-packed, stored_record_bytes each); most "
+                             "gathers hit L2/MALL"},
         "remap_kernel": {"ms_per_launch": round(rm_ms, 4), "record_bytes": rb,
                          "alg_bytes_per_launch": int(rm_bytes),
                          "achieved_GBs": round(rm_gbs, 1),
