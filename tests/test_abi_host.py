@@ -105,3 +105,29 @@ def test_record_width_from_dimensions(lib, dims, packed_words):
                                       _abi.make_opts(flags=_abi.UNPACKED_RECORDS))
     rec = lambda words: _align(nnz * 4 * (words + 1))
     assert wide - packed == 2 * (rec(N) - rec(packed_words))
+
+
+def test_python_constants_match_header():
+    """Flags, query ids, info keys and profiling ids in the binding carry the
+    header's values."""
+    src = open(os.path.join(ROOT, "include", "mttkrp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"#define\s+MTTKRP_([A-Z_0-9]+)\s+(\d+)u?\b", src)}
+    vals.update({m.group(1): int(m.group(2))
+                 for m in re.finditer(r"\bMTTKRP_([A-Z_0-9]+)\s*=\s*(\d+)", src)})
+    pairs = {"NO_IMPLICIT_REMAP": _abi.NO_IMPLICIT_REMAP, "NATURAL_ORDER": _abi.NATURAL_ORDER,
+             "FUSED_REMAP": _abi.FUSED_REMAP, "UNPACKED_RECORDS": _abi.UNPACKED_RECORDS,
+             "Q_LAYOUT": _abi.Q_LAYOUT, "Q_PERM": _abi.Q_PERM, "Q_ROW_PTR": _abi.Q_ROW_PTR,
+             "Q_SHARDS": _abi.Q_SHARDS, "Q_LPT": _abi.Q_LPT,
+             "INFO_CUR_MODE": _abi.INFO_CUR_MODE, "INFO_NSHARDS": _abi.INFO_NSHARDS,
+             "INFO_NSUPER": _abi.INFO_NSUPER, "INFO_NSPLIT": _abi.INFO_NSPLIT,
+             "INFO_G": _abi.INFO_G, "INFO_M": _abi.INFO_M, "INFO_RIDGE": _abi.INFO_RIDGE,
+             "INFO_RECORD_BYTES": _abi.INFO_RECORD_BYTES,
+             "PROF_MTTKRP": _abi.PROF_MTTKRP, "PROF_REMAP": _abi.PROF_REMAP,
+             "PROF_RESID": _abi.PROF_RESID, "PROF_LOSS": _abi.PROF_LOSS,
+             "F32": _abi.F32, "BF16": _abi.BF16, "OK": _abi.OK, "EINVAL": _abi.EINVAL,
+             "ERANGE": _abi.ERANGE, "ENOMEM": _abi.ENOMEM, "ESTATE": _abi.ESTATE,
+             "EHIP": _abi.EHIP}
+    for name, v in pairs.items():
+        assert vals.get(name) == v, (name, vals.get(name), v)
