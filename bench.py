@@ -1,26 +1,34 @@
 #!/usr/bin/env python3
 """All-mode sparse MTTKRP benchmark on one MI355X.
 
-Default workload (--config 2): a 3-mode COO tensor 50000 x 40000 x 30000
-with 20M distinct nonzeros (Zipf(1.2) coordinates over shuffled indices,
-lognormal(0,1) values), rank 32, N(0,1) FP32 factors.  One step is MTTKRP
-along all three modes, each followed by the dynamic remap of the tensor into
-the next mode's layout; the tensor ends where it started.
+Default workload (--config 3): a 4-mode COO tensor 1e6 x 5e5 x 2e4 x 2e3
+with 100M distinct nonzeros (Zipf(1.1) coordinates over shuffled indices,
+lognormal(0,1) values), rank 32, N(0,1) factors.  One step is MTTKRP along
+all four modes, each followed by the dynamic remap of the tensor into the
+next mode's layout; the tensor ends where it started.  The same sweep runs
+with FP32 factors (the headline) and with BF16-stored factors, and the
+outputs of both are compared with the FP64 oracle over every output row of
+every mode.
 
-Other workloads (explicit runs; parity and reporting, not the headline):
+Other workloads (explicit runs):
   --config 1  1000x800x600, 100K nnz, R=16: sweep + one CP-ALS sweep
-  --config 3  1e6x5e5x2e4x2e3, 100M nnz, R=32: FP32 and BF16 sweeps
+  --config 2  5e4x4e4x3e4, 20M nnz, Zipf(1.2), R=32: FP32 and BF16 sweeps
   --config 4  2e5^3, 50M nnz planted rank 64: sampled CP loss forward +
               autograd backward, finite differences on a 10K subsample
   --config 5  2e6x1e6x1e5x5e3x500, 200M nnz, R=16: full CP-ALS sweep, FP32
               and BF16
 
-Prints one JSON line: the sweep metric, the roofline of the per-mode MTTKRP
-kernel (algorithmic bytes per launch / mean launch time from HIP events, the
-compulsory-byte fraction, and the DRAM bytes from the committed rocprofv3
-counter summary when it was taken on the current kernel sources), the remap
-kernel, the FP64 oracle's single-core rate on a bounded sample, the BF16
-sweep with its errors, and the optional ablations.
+Prints one JSON line.  `value` is the HBM rate on compulsory bytes: every
+byte the sweep must move through HBM at least once (each stored record read
+and written by every mode's MTTKRP and remap, the remap targets, each factor
+read once per mode, each output written once) over the sweep time.  The
+paper's traffic model (every gathered factor row counted, most of which the
+L2 and Infinity Cache serve) is reported beside it as `model_GBs`.
+`roofline` is the per-mode MTTKRP kernel on its compulsory bytes per launch
+over its mean launch time (HIP events on the launch stream); `traffic` is
+the bytes its L2 fetched and wrote beyond itself (rocprofv3 FETCH_SIZE and
+WRITE_SIZE, calibrated on a plain copy), read from the committed counter
+summary when that was taken on the current kernel sources.
 """
 from __future__ import annotations
 
@@ -72,11 +80,17 @@ def b_alg_remap_kernel(dims, nnz, rb=None):
 
 
 def b_min_mttkrp_kernel(dims, nnz, R, n, sf, rb=None):
-    """Compulsory bytes: every stored record once, every input factor once,
-    the output."""
+    """Compulsory bytes of one MTTKRP launch: every stored record once,
+    every input factor once, the output once."""
     N = len(dims)
     rb = rec_bytes(N) if rb is None else rb
     return nnz * rb + sum(dims[w] * R * sf for w in range(N) if w != n) + dims[n] * R * 4
+
+
+def b_min_sweep_mode(dims, nnz, R, n, sf, rb):
+    """Compulsory bytes of mode n of a sweep: its MTTKRP launch plus the
+    remap (record read, remap target read, record write)."""
+    return b_min_mttkrp_kernel(dims, nnz, R, n, sf, rb) + nnz * (2 * rb + 4)
 
 
 def host_cpu():
@@ -145,27 +159,35 @@ class Timer:
         return e0.elapsed_time(e1) / steps
 
 
-def sampled_rows(T, rng, heavy=4, rand=28):
-    out = []
-    for n in range(T.nmodes):
-        counts = np.bincount(T.idx[n], minlength=T.dims[n])
-        top = np.argsort(counts)[-heavy:]
-        r = rng.choice(T.dims[n], min(rand, T.dims[n]), replace=False)
-        out.append(np.unique(np.concatenate([top, r])))
-    return out
+def oracle_all_modes(oracle, T, threads):
+    """FP64 oracle MTTKRP of every mode over every nonzero, with the |.|-sum
+    M^abs used as the elementwise error scale.  One thread per mode (the
+    oracle is single-threaded C; ctypes releases the GIL during the call)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=max(1, min(threads, T.nmodes))) as ex:
+        futs = [ex.submit(oracle.mttkrp, T.dims, T.idx, T.vals, T.factors, n, True)
+                for n in range(T.nmodes)]
+        refs = [f.result() for f in futs]
+    return refs, time.time() - t0
 
 
-def error_report(oracle, T, factors64, outs, samples, torch, dev):
-    """Per mode: normwise and |.|-scaled elementwise error on sampled rows
-    against the FP64 oracle (each sampled row computed one by one)."""
+def error_report(refs, outs, tol):
+    """Per mode, over every output row: normwise error, the largest
+    |got - ref| / M^abs, and the largest absolute error against the FP64
+    oracle; `ok` says whether both relative figures are within tol (rows
+    without nonzeros must be exactly zero)."""
     rep = []
-    for n in range(T.nmodes):
-        ref, rabs = oracle.mttkrp_rows(T.dims, T.idx, T.vals, factors64, n, samples[n])
-        got = outs[n][torch.from_numpy(samples[n]).to(dev)].cpu().numpy().astype(np.float64)
+    for (ref, rabs), got in zip(refs, outs):
+        got = got.astype(np.float64)
+        d = np.abs(got - ref)
         nw = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
-        el = float(np.max(np.abs(got - ref) / np.where(rabs > 0, rabs, 1)))
-        rep.append({"normwise": nw, "elementwise_vs_abs": el,
-                    "max_abs": float(np.abs(got - ref).max())})
+        zero = rabs == 0
+        el = float(np.max(np.where(zero, 0.0, d / np.where(zero, 1.0, rabs))))
+        nonzero_where_zero = int(np.count_nonzero(got[zero]))
+        rep.append({"rows": int(ref.shape[0]), "normwise": nw, "elementwise_vs_abs": el,
+                    "max_abs": float(d.max()) if d.size else 0.0,
+                    "ok": bool(nw <= tol and el <= tol and nonzero_where_zero == 0)})
     return rep
 
 
@@ -173,7 +195,7 @@ def error_report(oracle, T, factors64, outs, samples, torch, dev):
 def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
     w = syn.WORKLOADS[args.config]
     t0 = time.time()
-    T = syn.generate(args.config, progress=log)
+    T = syn.generate(args.config, cache_dir=args.cache_dir, progress=log)
     log(f"generated {w.name}: nnz={T.nnz} in {time.time() - t0:.1f}s")
     dims, R, N, nnz = T.dims, T.rank, T.nmodes, T.nnz
     idx = torch.from_numpy(T.idx).to(dev)
@@ -210,12 +232,21 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         plan.profile(False)
         return ms, per_mode, per_remap
 
+    # the FP64 oracle over every nonzero of every mode, one thread per mode,
+    # in the background while the GPU is timed (joined before the errors)
+    from concurrent.futures import ThreadPoolExecutor
+    opool = ThreadPoolExecutor(max_workers=1)
+    ofut = None if args.no_errors else opool.submit(oracle_all_modes, oracle, T,
+                                                    args.oracle_threads)
+
     sweep_ms, per_mode, per_remap = timed(f32)
     log(f"fp32 sweep {sweep_ms:.3f} ms; MTTKRP kernel ms "
         f"{[round(m / max(c, 1), 4) for m, c in per_mode]}; remap kernel ms "
         f"{[round(m / max(c, 1), 4) for m, c in per_remap]}")
-    sweep_bytes = sum(b_alg_mode(dims, nnz, R, n, 4) for n in range(N))
-    value = sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    rb = plan.info(_abi.INFO_RECORD_BYTES)       # stored record bytes
+    sweep_min = sum(b_min_sweep_mode(dims, nnz, R, n, 4, rb) for n in range(N))
+    sweep_model = sum(b_alg_mode(dims, nnz, R, n, 4) for n in range(N))
+    value = sweep_min / (sweep_ms * 1e-3) / 1e9
     # per-step distribution, and one sweep after a 512 MiB scratch write
     # (factor rows no longer in L2 or the Infinity Cache)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -245,33 +276,67 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         return ms / max(launches, 1), nbytes / max(launches, 1), \
             nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
 
-    mk_ms, mk_bytes, mk_gbs = kstats(per_mode, lambda n: b_alg_mttkrp_kernel(dims, nnz, R, n, 4))
-    rb = plan.info(_abi.INFO_RECORD_BYTES)       # stored record bytes
+    mk_ms, mk_min, mk_gbs = kstats(per_mode, lambda n: b_min_mttkrp_kernel(dims, nnz, R, n, 4, rb))
+    _, mk_model, mk_model_gbs = kstats(per_mode,
+                                       lambda n: b_alg_mttkrp_kernel(dims, nnz, R, n, 4))
     rm_ms, rm_bytes, rm_gbs = kstats(per_remap, lambda n: b_alg_remap_kernel(dims, nnz, rb))
-    mk_min = sum(b_min_mttkrp_kernel(dims, nnz, R, n, 4, rb) for n in range(N)) / N
     ctr = os.path.join(ROOT, "profiles", f"mttkrp_kernel_{w.name}_counters.txt")
     fetch = counter_traffic(ctr, "fetch_bytes_per_launch")
     write = counter_traffic(ctr, "write_bytes_per_launch")
     traffic = (fetch + write) if (fetch is not None and write is not None) else None
 
-    rng = np.random.default_rng(0)
-    samples = sampled_rows(T, rng)
     plan.mttkrp_all_modes(f32, outs)
     torch.cuda.synchronize()
-    err32 = error_report(oracle, T, T.factors, outs, samples, torch, dev)
+    got32 = [o.cpu().numpy() for o in outs]
 
     result_bf16 = None
+    gotb = None
     if not args.no_bf16:
         bms, bmode, bremap = timed(bf)
         plan.mttkrp_all_modes(bf, outs)
         torch.cuda.synchronize()
-        errb = error_report(oracle, T, T.factors, outs, samples, torch, dev)
-        bbytes = sum(b_alg_mode(dims, nnz, R, n, 2) for n in range(N))
+        gotb = [o.cpu().numpy() for o in outs]
+        bmin = sum(b_min_sweep_mode(dims, nnz, R, n, 2, rb) for n in range(N))
+        bmodel = sum(b_alg_mode(dims, nnz, R, n, 2) for n in range(N))
         result_bf16 = {"sweep_ms": round(bms, 4), "speedup_vs_fp32": round(sweep_ms / bms, 3),
-                       "alg_GBs": round(bbytes / (bms * 1e-3) / 1e9, 1),
+                       "GBs": round(bmin / (bms * 1e-3) / 1e9, 1),
+                       "model_GBs": round(bmodel / (bms * 1e-3) / 1e9, 1),
                        "mttkrp_kernel_ms": [round(m / max(c, 1), 4) for m, c in bmode],
-                       "error_vs_fp64_oracle": errb, "tolerance": 2e-2}
+                       "remap_kernel_ms": [round(m / max(c, 1), 4) for m, c in bremap],
+                       "tolerance": 2e-2}
         log(f"bf16 sweep {bms:.3f} ms (x{sweep_ms / bms:.2f})")
+
+    # gather ceiling: a kernel that issues the MTTKRP kernel's record loads and
+    # factor-row gathers (same lane form, same row reuse) and reduces them
+    # trivially; the MTTKRP kernel's time over it says how much of the time
+    # the gathers themselves take
+    ceiling = None
+    if not args.no_ablation:
+        gplan = Plan(idx, vals, dims, R, g=args.g, flags=flags | _abi.GATHER_ONLY)
+        gouts = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in dims]
+        ceiling = {}
+        for name, F, kt in (("fp32", f32, per_mode),
+                            ("bf16", bf, bmode if result_bf16 else None)):
+            if kt is None:
+                continue
+            for _ in range(args.warmup):
+                gplan.mttkrp_all_modes(F, gouts)
+            torch.cuda.synchronize()
+            gplan.profile(True)
+            for _ in range(args.steps):
+                gplan.mttkrp_all_modes(F, gouts)
+            torch.cuda.synchronize()
+            gk = [gplan.profile_read(_abi.PROF_MTTKRP, n) for n in range(N)]
+            gplan.profile_read(_abi.PROF_REMAP)
+            gplan.profile(False)
+            g_ms = sum(m for m, _ in gk) / max(sum(c for _, c in gk), 1)
+            k_ms = sum(m for m, _ in kt) / max(sum(c for _, c in kt), 1)
+            ceiling[name] = {"gather_ceiling_ms": round(g_ms, 4),
+                             "mttkrp_kernel_ms": round(k_ms, 4),
+                             "kernel_over_ceiling": round(k_ms / g_ms, 3)}
+            log(f"gather ceiling {name}: {g_ms:.4f} ms per launch; MTTKRP kernel "
+                f"{k_ms:.4f} ms (x{k_ms / g_ms:.3f})")
+        del gplan, gouts
 
     # the paper's "without remapping" baseline: one tensor copy per mode
     # layout (N x the memory), so each mode's MTTKRP runs with no remap;
@@ -374,6 +439,18 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         ablations["m_sweep"] = rows
 
     del idx, vals
+    err32, oracle_s = None, None
+    if ofut is not None:
+        refs, oracle_s = ofut.result()
+        err32 = error_report(refs, got32, 1e-5)
+        log(f"fp32 errors over every row: {err32}")
+        if gotb is not None:
+            result_bf16["error_vs_fp64_oracle"] = error_report(refs, gotb, 2e-2)
+            log(f"bf16 errors over every row: {result_bf16['error_vs_fp64_oracle']}")
+        del refs
+    opool.shutdown()
+    del got32, gotb
+
     cpu = None
     if not args.no_cpu_baseline:
         # the FP64 oracle on one core, on a bounded sample of the same tensor
@@ -382,14 +459,16 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         for n in range(N):
             oracle.mttkrp(dims, T.idx[:, :S], T.vals[:S], T.factors, n)
         cs = time.time() - tc
-        sb = sum(b_alg_mode(dims, S, R, n, 4) for n in range(N))
+        sb = sum(b_min_sweep_mode(dims, S, R, n, 4, rb) for n in range(N))
         what = "all" if S == nnz else f"the first {S} (in generation order) of {nnz}"
         cpu = {"value": round(sb / cs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sweep_s": round(cs, 2), "host": host_cpu(),
                "sample": f"FP64 oracle MTTKRP along all {N} modes over {what} nonzeros, "
-                         f"single thread; value = paper-model bytes of that sample / time"}
+                         f"single thread; value = the compulsory sweep bytes of that "
+                         f"sample (as for the GPU value) / time"}
         log(f"oracle sweep {cs:.1f} s on one core ({S} nonzeros)")
 
+    tr_gbs = traffic / (mk_ms * 1e-3) / 1e9 if traffic else None
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -400,31 +479,42 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
                    "step": "MTTKRP along every mode, each followed by the dynamic "
                            "remap of the tensor into the next mode's layout",
                    "shard_g": plan.info(_abi.INFO_G), "plan_ms": round(plan_ms, 1)},
+        "value_is": "compulsory HBM bytes of the sweep (stored records read and written "
+                    "by every mode's MTTKRP and remap, remap targets, each factor once "
+                    "per mode, outputs) / sweep time",
+        "model_GBs": round(sweep_model / (sweep_ms * 1e-3) / 1e9, 1),
+        "model_GBs_is": "the paper's traffic model (every gathered factor row, 4N+4-byte "
+                        "records) / sweep time; most gathers are served by L2 and the "
+                        "Infinity Cache, so this exceeds the HBM peak",
         "roofline": {"bound": "hbm", "achieved": round(mk_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(mk_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "mk::mttkrp_kernel (per-mode MTTKRP)",
                      "kernel_ms_per_launch": round(mk_ms, 4),
-                     "alg_bytes_per_launch": int(mk_bytes),
                      "compulsory_bytes_per_launch": int(mk_min),
-                     "compulsory_frac": round(mk_min / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic_GBs": round(traffic / (mk_ms * 1e-3) / 1e9, 1) if traffic else None,
-                     "traffic_frac": round(traffic / (mk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                     if traffic else None,
-                     "stored_record_bytes": rb,
-                     "note": "algorithmic bytes count every gathered factor row and "
-                             "4N+4-byte records (paper's traffic model; the stored "
-                             "records are bit-packed, stored_record_bytes each); most "
-                             "gathers hit L2/MALL"},
+                     "achieved_is": "compulsory bytes per launch (stored records once, "
+                                    "each input factor once, the output once) / mean "
+                                    "launch time from HIP events on the launch stream",
+                     "model_bytes_per_launch": int(mk_model),
+                     "model_GBs": round(mk_model_gbs, 1),
+                     "traffic_is": "bytes the L2 fetched from and wrote to the fabric per "
+                                   "launch (FETCH_SIZE x2 + WRITE_SIZE, calibrated on a plain "
+                                   "copy); Infinity-Cache hits included, so an upper bound "
+                                   "on DRAM bytes",
+                     "beyond_l2_GBs": round(tr_gbs, 1) if tr_gbs else None,
+                     "stored_record_bytes": rb},
+        "gather_ceiling": ceiling,
         "remap_kernel": {"ms_per_launch": round(rm_ms, 4), "record_bytes": rb,
-                         "alg_bytes_per_launch": int(rm_bytes),
+                         "bytes_per_launch": int(rm_bytes),
                          "achieved_GBs": round(rm_gbs, 1),
                          "frac": round(rm_gbs / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
+        "oracle_error_run_s": round(oracle_s, 1) if oracle_s else None,
         "sweep_ms": round(sweep_ms, 4),
         "per_mode_kernel_ms": [round(m / max(c, 1), 4) for m, c in per_mode],
         "per_mode_remap_ms": [round(m / max(c, 1), 4) for m, c in per_remap],
         "fp32_error_vs_fp64_oracle": err32,
+        "fp32_tolerance": 1e-5,
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
         "unpacked_records_sweep_ms": round(unpacked_ms, 4) if unpacked_ms else None,
@@ -437,7 +527,8 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "remap_share": {
             "of_sweep_time": round(sum(m for m, _ in per_remap) / max(sum(c for _, c in per_remap), 1)
                                    * N / sweep_ms, 4),
-            "of_alg_bytes": round(sum(nnz * rec_bytes(N) for _ in range(N)) / sweep_bytes, 4)},
+            "of_compulsory_bytes": round(N * nnz * (2 * rb + 4) / sweep_min, 4),
+            "of_model_bytes": round(sum(nnz * rec_bytes(N) for _ in range(N)) / sweep_model, 4)},
         "ablations": ablations or None,
     }
     return rec
@@ -512,7 +603,7 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
     from paper_2309_09131_amd.api import cp_loss
     w = syn.WORKLOADS[4]
     t0 = time.time()
-    T = syn.generate(4, progress=log)
+    T = syn.generate(4, cache_dir=args.cache_dir, progress=log)
     log(f"generated {w.name}: nnz={T.nnz} in {time.time() - t0:.1f}s")
     dims, R, N, nnz = T.dims, T.rank, T.nmodes, T.nnz
     idx = torch.from_numpy(T.idx).to(dev)
@@ -651,15 +742,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--g", type=int, default=0)
     ap.add_argument("--natural-order", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the FP64 oracle run over every output (profiling runs)")
+    ap.add_argument("--cache-dir", default=None,
+                    help="directory for the generated tensor (.npz), reused when present")
     ap.add_argument("--no-ablation", action="store_true",
-                    help="skip the fused-remap ablation sweep")
-    ap.add_argument("--cpu-sample", type=int, default=20_000_000,
+                    help="skip the gather ceiling and the fused-remap and unpacked-record "
+                         "sweeps")
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
                     help="nonzeros the CPU oracle baseline processes at most")
+    ap.add_argument("--oracle-threads", type=int, default=8,
+                    help="threads (one per mode) of the full FP64 oracle run that "
+                         "gives the errors over every output row")
     ap.add_argument("--copy-calib-mb", type=int, default=256,
                     help="size of a plain device copy run for counter calibration")
     ap.add_argument("--rank-sweep", default="",

@@ -32,7 +32,8 @@
  *     outputs and gradients are FP32, row-major I_n x R.
  *   - Errors are status codes; nothing aborts or throws across the ABI.
  *     Argument errors are detected on the host before any device work.
- *   - Limits: 2 <= N <= 8, 1 <= R <= 256, 1 <= I_n < 2^31, nnz < 2^31.
+ *   - Limits: 2 <= N <= 8, 1 <= R <= 256, 1 <= I_n < 2^31,
+ *     0 <= nnz <= MTTKRP_MAX_NNZ (2^31 - 2^20).
  *   - Results are deterministic: no global atomics, fixed reduction order,
  *     so repeated calls give bit-identical outputs.
  */
@@ -48,6 +49,10 @@ extern "C" {
 
 #define MTTKRP_MAX_MODES 8
 #define MTTKRP_MAX_RANK 256
+/* Largest nnz a plan accepts: 2^31 - 2^20.  Kernels index nonzeros with
+ * 32-bit integers and form indices a few hundred past a shard's end before
+ * clamping them, so the margin keeps every such index below 2^31. */
+#define MTTKRP_MAX_NNZ 2146435072
 
 typedef struct mttkrp_plan_s *mttkrp_plan_t;
 
@@ -75,6 +80,16 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
                                         stored records instead of the default
                                         bit-packed form (see the workspace
                                         description); for comparison       */
+#define MTTKRP_GATHER_ONLY 16u       /* measurement only: MTTKRP passes run a
+                                        kernel that issues the MTTKRP kernel's
+                                        record loads and factor-row gathers
+                                        (same lanes, same row reuse) but adds
+                                        every product into one register; the
+                                        outputs are NOT MTTKRP results.  Its
+                                        time bounds the MTTKRP kernel's from
+                                        below for the same access stream.
+                                        Needs the contiguous lane forms (R a
+                                        multiple of 4 for FP32, 8 for BF16). */
 
 /* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
 typedef struct {

@@ -15,12 +15,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmttkrp.so")
 
 MAX_MODES = 8
+MAX_NNZ = (1 << 31) - (1 << 20)   # MTTKRP_MAX_NNZ
 OK, EINVAL, ERANGE, ENOMEM, ESTATE, EHIP = range(6)
 F32, BF16 = 0, 1
 NO_IMPLICIT_REMAP = 1
 NATURAL_ORDER = 2
 FUSED_REMAP = 4
 UNPACKED_RECORDS = 8
+GATHER_ONLY = 16
 PROF_MTTKRP, PROF_REMAP, PROF_RESID, PROF_LOSS = 0, 1, 2, 3
 Q_LAYOUT, Q_PERM, Q_ROW_PTR, Q_SHARDS, Q_LPT = range(5)
 INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2

@@ -45,21 +45,29 @@ template <int W, typename FT, int LANES, int V, bool STRIDED>
 hipError_t launch_one(const Args &a, int kind, unsigned grid, hipStream_t s)
 {
     // separate instantiations with and without the in-kernel remap
+    const dim3 blk(MTT_WAVES * 64);
     if (kind == KIND_MTTKRP && a.rout)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, false, true>),
-                           dim3(grid), dim3(MTT_WAVES * 64), 0, s, a);
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_MTTKRP, true>),
+                           dim3(grid), blk, 0, s, a);
     else if (kind == KIND_MTTKRP)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, false, false>),
-                           dim3(grid), dim3(MTT_WAVES * 64), 0, s, a);
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_MTTKRP, false>),
+                           dim3(grid), blk, 0, s, a);
     else if (kind == KIND_RESID && a.rout)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, true, true>),
-                           dim3(grid), dim3(MTT_WAVES * 64), 0, s, a);
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_RESID, true>),
+                           dim3(grid), blk, 0, s, a);
     else if (kind == KIND_RESID)
-        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, true, false>),
-                           dim3(grid), dim3(MTT_WAVES * 64), 0, s, a);
-    else
-        hipLaunchKernelGGL((loss_kernel<NM, W, FT, LANES, V, STRIDED>), dim3(grid), dim3(256), 0,
-                           s, a);
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_RESID, false>),
+                           dim3(grid), blk, 0, s, a);
+    else if (kind == KIND_LOSS)
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_LOSS, false>),
+                           dim3(grid), blk, 0, s, a);
+    else if (kind == KIND_GATHER) {
+        if constexpr (STRIDED) return hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_GATHER, false>),
+                               dim3(grid), blk, 0, s, a);
+    } else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -49,7 +49,9 @@ struct LaneCfg {
     bool strided;
 };
 
-enum Kind { KIND_MTTKRP = 0, KIND_RESID = 1, KIND_LOSS = 2 };
+// KIND_GATHER: the MTTKRP kernel's loads without its segmented reduction
+// (measurement only; contiguous lane forms).
+enum Kind { KIND_MTTKRP = 0, KIND_RESID = 1, KIND_LOSS = 2, KIND_GATHER = 3 };
 
 template <int N>
 hipError_t launch_mttkrp(const Args &a, int bf16, LaneCfg c, int kind, unsigned grid,

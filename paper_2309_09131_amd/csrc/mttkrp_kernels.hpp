@@ -1,7 +1,7 @@
 // Per-mode sparse MTTKRP (optionally with the dynamic remap in the same
-// pass), the residual (loss-gradient) variant, the sampled-loss forward, and
-// the standalone remap, templated on the number of modes N and the factor
-// storage type.
+// pass), the residual (loss-gradient) variant and the sampled-loss forward,
+// which share one kernel template, and the standalone remap, templated on
+// the number of modes N and the factor storage type.
 //
 // Work decomposition.  The tensor buffer holds layout L_n: nonzeros
 // contiguous by output row c_n (Sec. III-B).  The plan cuts it into shards
@@ -222,23 +222,6 @@ __device__ __forceinline__ void row_product(const Inputs<N> &in, const Rec<W> &r
     }
 }
 
-// Product over all N modes (loss forward).
-template <int N, int W, typename FT, int V, bool STRIDED>
-__device__ __forceinline__ void row_product_all(const Args &a, const Rec<W> &rc, int R, int sub,
-                                                float (&pr)[V])
-{
-#pragma unroll
-    for (int j = 0; j < V; ++j) pr[j] = 1.0f;
-#pragma unroll
-    for (int w = 0; w < N; ++w) {
-        float x[V];
-        Fetch<FT, V, STRIDED>::get(a.fac[w], (int64_t)rec_coord<W>(rc, a.coff[w], a.cmask[w]), R,
-                                   sub, x);
-#pragma unroll
-        for (int j = 0; j < V; ++j) pr[j] *= x[j];
-    }
-}
-
 // Sum over the LANES lanes of one slot (xor butterfly stays inside the slot).
 template <int LANES>
 __device__ __forceinline__ float slot_sum(float v)
@@ -248,16 +231,33 @@ __device__ __forceinline__ float slot_sum(float v)
     return v;
 }
 
-// ---- per-mode MTTKRP (RESID = false) / loss-gradient pass (RESID = true) --
+// ---- per-mode MTTKRP family ---------------------------------------------
+// KIND (a Kind of launch.hpp):
+//   KIND_MTTKRP  M_n(i,:) = sum_e v_e * prod_{w != n} A_w(c_w(e), :)
+//   KIND_RESID   loss-gradient pass: the same sum with v_e replaced by
+//                -2 s rho_e, rho_e = v_e - m_e recomputed from the model
+//                value m_e = sum_r A_n(c_n(e), r) prod_{w != n} A_w(c_w(e), r)
+//   KIND_LOSS    loss forward: sum_e rho_e^2, one FP64 partial per shard
+//                (FP32 terms, FP64 accumulation); no output rows
+//   KIND_GATHER  measurement only: the same record loads, factor-row
+//                gathers, row reuse and products, but every product is added
+//                into one register per lane and stored to the shard's first
+//                output row, with no segmentation; its time is the cost of
+//                the loads themselves, a ceiling for this kernel
+//
 // The wave's shard is cut into SW equal contiguous runs, one per slot.  A
 // slot walks its run in order, U nonzeros per iteration (all their loads
 // issued before the first use), accumulating the current row in registers:
 // a row that starts and ends inside the run is complete and written at
 // once.  The first row of each run (head) and the last (tail) are then
 // joined across slots with one segmented scan per shard.
-template <int N, int W, typename FT, int LANES, int V, bool STRIDED, bool RESID, bool FUSE>
+template <int N, int W, typename FT, int LANES, int V, bool STRIDED, int KIND, bool FUSE>
 __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 {
+    constexpr bool RESID = KIND == KIND_RESID;
+    constexpr bool LOSS = KIND == KIND_LOSS;
+    constexpr bool GONLY = KIND == KIND_GATHER;
+    constexpr bool MODEL = RESID || LOSS;        // m_e needed: output row gathered too
     constexpr int SW = WAVE / LANES;
     // nonzeros per step of a lane group: 4 measured fastest (2 and 3 keep
     // fewer gathers in flight; 8 halves the waves per SIMD and is slower)
@@ -329,6 +329,16 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     // slot with cross-lane moves.  The vector-memory path (misses in flight
     // per CU) limits this kernel, so duplicate loads are expensive.  The
     // next group's records are loaded while the current group computes.
+    // The loss kinds also need the output-mode row of every nonzero for the
+    // model value.  It is constant along a run of one output row (about
+    // nnz / I_n nonzeros), so it is likewise loaded only when the row changes
+    // (contiguous lane forms).
+    constexpr bool OREUSE = MODEL && !STRIDED;
+    uint32_t xo[RW];
+    int po = -1;
+#pragma unroll
+    for (int j = 0; j < RW; ++j) xo[j] = 0u;
+    double lacc = 0.0;                            // KIND_LOSS: sum of rho^2
     constexpr int RPL = (U + LANES - 1) / LANES;
     Rec<W> nxt[RPL];
 #pragma unroll
@@ -357,6 +367,25 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
         }
         float pr[U][V];
         float mm[U];
+        uint32_t xq[OREUSE ? U : 1][RW];
+        bool ndo[U];
+        if constexpr (OREUSE) {
+            int co[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                co[u] = rec_coord<W>(rc[u], noff, nmsk);
+                ndo[u] = ok[u] && co[u] != (u == 0 ? po : co[u - 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int j = 0; j < RW; ++j) xq[u][j] = 0u;
+                if (ndo[u]) RawRow<FT, V>::get(a.fac[n], (int64_t)co[u], R, fsub, xq[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) po = co[u];
+        }
         if constexpr (REUSE) {
             int cc[NR][U];
             bool need[NR][U];
@@ -408,14 +437,35 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             mm[u] = 0.0f;
-            if constexpr (RESID) {
+            if constexpr (MODEL) {
                 float xn[V];
-                Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)rec_coord<W>(rc[u], noff, nmsk), R,
-                                           fsub, xn);
+                if constexpr (OREUSE) {
+                    int sel = ndo[u] ? 1 : 0;        // opaque, as for the input rows
+                    asm volatile("" : "+v"(sel));
+#pragma unroll
+                    for (int j = 0; j < RW; ++j) xo[j] = sel ? xq[u][j] : xo[j];
+                    RawRow<FT, V>::unpack(xo, xn);
+                } else {
+                    Fetch<FT, V, STRIDED>::get(a.fac[n],
+                                               (int64_t)rec_coord<W>(rc[u], noff, nmsk), R,
+                                               fsub, xn);
+                }
 #pragma unroll
                 for (int j = 0; j < V; ++j) mm[u] += pr[u][j] * xn[j];
                 if (!(ok[u] && ract)) mm[u] = 0.0f;
             }
+        }
+        if constexpr (LOSS) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                // model value m_e (lanes outside the rank range hold 0)
+                const float m = slot_sum<LANES>(mm[u]);
+                if (ok[u] && sub == 0) {
+                    const float rho = __uint_as_float(rc[u].w[W]) - m;
+                    lacc += (double)(rho * rho);  // FP32 term, FP64 accumulation
+                }
+            }
+            continue;
         }
         if constexpr (FUSE) {
             int dst[U];
@@ -434,6 +484,13 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                 if (ok[u]) c = coef * (__uint_as_float(rc[u].w[W]) - m);
             } else {
                 if (ok[u]) c = __uint_as_float(rc[u].w[W]);
+            }
+            if constexpr (GONLY) {
+                if (ok[u]) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) acc[j] += c * pr[u][j];
+                }
+                continue;
             }
             if (ok[u]) {
                 const int row = rec_coord<W>(rc[u], noff, nmsk);
@@ -454,6 +511,15 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                 for (int j = 0; j < V; ++j) acc[j] += c * pr[u][j];
             }
         }
+    }
+    if constexpr (LOSS) {
+        lacc = wave_sum_d(lacc);
+        if (lane == 0) a.partial[shard] = lacc;
+        return;
+    }
+    if constexpr (GONLY) {
+        if (ract) store_row<V, STRIDED>(out + (int64_t)f * R, R, sub, acc);
+        return;
     }
     const bool single = in_head;                 // whole run is one row
     const int tail_row = cur_row;
@@ -505,53 +571,6 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
         }
     }
 #undef FLUSH_MID
-}
-
-// ---- sampled CP loss forward: one double partial per shard ---------------
-template <int N, int W, typename FT, int LANES, int V, bool STRIDED>
-__global__ __launch_bounds__(256) void loss_kernel(Args a)
-{
-    constexpr int SW = WAVE / LANES;
-    constexpr int U = 4;
-    const int lane = threadIdx.x & 63;
-    const int sidx = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (sidx >= a.nshards) return;
-    const int start = a.shards[3 * sidx];
-    const int end = start + a.shards[3 * sidx + 1];
-    const int R = a.R;
-    const int slot = lane / LANES, sub = lane % LANES;
-    const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
-    double acc = 0.0;
-    for (int base = start; base < end; base += U * SW) {
-        Rec<W> rc[U];
-        float m[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * SW + slot;
-            rc[u] = load_rec<W>(a.rin, e < end ? e : start);   // clamped, no branch
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * SW + slot;
-            float pr[V];
-            row_product_all<N, W, FT, V, STRIDED>(a, rc[u], R, ract ? sub : 0, pr);
-            m[u] = 0.0f;
-#pragma unroll
-            for (int j = 0; j < V; ++j) m[u] += pr[j];
-            if (!(e < end && ract)) m[u] = 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = base + u * SW + slot;
-            const float mu = slot_sum<LANES>(m[u]);
-            if (e < end && sub == 0) {
-                const float rho = __uint_as_float(rc[u].w[W]) - mu;
-                acc += (double)(rho * rho);    // FP32 term, FP64 accumulation
-            }
-        }
-    }
-    acc = wave_sum_d(acc);
-    if (lane == 0) a.partial[sidx] = acc;
 }
 
 // ---- standalone remap: L_{n+1}[P_n[i]] = L_n[i] -------------------------

@@ -71,7 +71,12 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     if (N < 2 || N > MTTKRP_MAX_MODES) { *why = "nmodes must be in [2, 8]"; return MTTKRP_EINVAL; }
     if (!dims) { *why = "dims is NULL"; return MTTKRP_EINVAL; }
     if (R < 1 || R > MTTKRP_MAX_RANK) { *why = "rank must be in [1, 256]"; return MTTKRP_EINVAL; }
-    if (nnz < 0 || nnz >= (int64_t(1) << 31)) { *why = "nnz must be in [0, 2^31)"; return MTTKRP_EINVAL; }
+    // the kernels index nonzeros with 32-bit integers and may form indices
+    // up to a few hundred past the end of a shard before clamping them
+    if (nnz < 0 || nnz > MTTKRP_MAX_NNZ) {
+        *why = "nnz must be in [0, " + std::to_string((long long)MTTKRP_MAX_NNZ) + "]";
+        return MTTKRP_EINVAL;
+    }
     memset(L, 0, sizeof(*L));
     L->N = N; L->nnz = nnz; L->R = R;
     L->g = (opts && opts->g > 0) ? opts->g : DEFAULT_G;
@@ -705,7 +710,12 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.gscale = gscale;
     a.partial = p->rt<double>(L.rt_partial);
     const mk::LaneCfg c = lane_cfg(L.R, fdt, facs, L.N, out);
-    const int wpb = kind == mk::KIND_LOSS ? 4 : mk::MTT_WAVES;   // shards per workgroup
+    // measurement plans: the MTTKRP kernel's loads only (contiguous lanes)
+    const bool gonly = kind == mk::KIND_MTTKRP && (L.flags & MTTKRP_GATHER_ONLY);
+    if (gonly && c.strided)
+        return fail(p, MTTKRP_EINVAL, "MTTKRP_GATHER_ONLY needs R a multiple of 4 (FP32) or 8 "
+                                      "(BF16) and 16-byte aligned factors");
+    const int wpb = mk::MTT_WAVES;   // shards (waves) per workgroup
     const unsigned grid = (unsigned)((p->nshards[n] + wpb - 1) / wpb);
     const int pk = kind == mk::KIND_MTTKRP  ? MTTKRP_PROF_MTTKRP
                    : kind == mk::KIND_RESID ? MTTKRP_PROF_RESID
@@ -717,7 +727,7 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         ev.b = take_event(p);
         if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
     }
-    const bool seg = kind != mk::KIND_LOSS && p->npart[n] > 0;
+    const bool seg = kind != mk::KIND_LOSS && !gonly && p->npart[n] > 0;
     if (seg) {
         mttkrp_status st = ensure_aux(p);
         if (st != MTTKRP_OK) return st;
@@ -726,7 +736,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         p->seg_pending[cs] = false;
         p->carry_sel ^= 1;
     }
-    HIPCHK(p, launch_mttkrp_any(L.N, a, fdt == MTTKRP_BF16, c, kind, grid, s));
+    HIPCHK(p, launch_mttkrp_any(L.N, a, fdt == MTTKRP_BF16, c, gonly ? mk::KIND_GATHER : kind,
+                                grid, s));
     if (prof) {
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);

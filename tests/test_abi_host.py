@@ -47,6 +47,21 @@ def test_workspace_argument_errors(lib):
         _abi.mttkrp_plan_workspace(3, (10, 20, 30), 5, 4, _abi.make_opts(g=-1))
 
 
+def test_nnz_limit_keeps_kernel_indices_in_int32(lib):
+    """Kernels index nonzeros with 32-bit integers and may step a few hundred
+    past a shard's end before clamping, so the plan refuses nnz above
+    MTTKRP_MAX_NNZ = 2^31 - 2^20 (sizes only: no device work)."""
+    assert _abi.MAX_NNZ == (1 << 31) - (1 << 20)
+    dims = (1 << 20, 1 << 20, 1 << 20)
+    for nnz in ((1 << 31) - 1, (1 << 31) - 256, _abi.MAX_NNZ + 1):
+        with pytest.raises(_abi.MttkrpError) as ei:
+            _abi.mttkrp_plan_workspace(3, dims, nnz, 16)
+        assert ei.value.status == _abi.EINVAL, nnz
+        assert str(_abi.MAX_NNZ) in str(ei.value)
+    need = _abi.mttkrp_plan_workspace(3, dims, _abi.MAX_NNZ, 16)
+    assert need > 2 * _abi.MAX_NNZ * 12
+
+
 def test_plan_argument_errors_before_device_work(lib):
     dims = (10, 20, 30)
     need = _abi.mttkrp_plan_workspace(3, dims, 100, 8)
@@ -118,6 +133,7 @@ def test_python_constants_match_header():
                  for m in re.finditer(r"\bMTTKRP_([A-Z_0-9]+)\s*=\s*(\d+)", src)})
     pairs = {"NO_IMPLICIT_REMAP": _abi.NO_IMPLICIT_REMAP, "NATURAL_ORDER": _abi.NATURAL_ORDER,
              "FUSED_REMAP": _abi.FUSED_REMAP, "UNPACKED_RECORDS": _abi.UNPACKED_RECORDS,
+             "GATHER_ONLY": _abi.GATHER_ONLY,
              "Q_LAYOUT": _abi.Q_LAYOUT, "Q_PERM": _abi.Q_PERM, "Q_ROW_PTR": _abi.Q_ROW_PTR,
              "Q_SHARDS": _abi.Q_SHARDS, "Q_LPT": _abi.Q_LPT,
              "INFO_CUR_MODE": _abi.INFO_CUR_MODE, "INFO_NSHARDS": _abi.INFO_NSHARDS,
@@ -126,6 +142,7 @@ def test_python_constants_match_header():
              "INFO_RECORD_BYTES": _abi.INFO_RECORD_BYTES,
              "PROF_MTTKRP": _abi.PROF_MTTKRP, "PROF_REMAP": _abi.PROF_REMAP,
              "PROF_RESID": _abi.PROF_RESID, "PROF_LOSS": _abi.PROF_LOSS,
+             "MAX_NNZ": _abi.MAX_NNZ, "MAX_MODES": _abi.MAX_MODES,
              "F32": _abi.F32, "BF16": _abi.BF16, "OK": _abi.OK, "EINVAL": _abi.EINVAL,
              "ERANGE": _abi.ERANGE, "ENOMEM": _abi.ENOMEM, "ESTATE": _abi.ESTATE,
              "EHIP": _abi.EHIP}
