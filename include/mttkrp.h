@@ -198,6 +198,28 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors,
                            double *d_fit, void *stream);
 
 /*
+ * The CP-ALS sweep of cp_als_sweep without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The FP32 scratch that
+ * cp_als_sweep takes as d_mbuf is instead a static device array of
+ * MTTKRP_STATIC_MBUF_FLOATS floats (64 MiB) inside the library; every GPU
+ * the library runs on holds its own copy until the process ends.  The call
+ * allocates nothing and creates no HIP objects: the plan made its stream
+ * and events when it was built, and kernel timing (mttkrp_profile) is not
+ * applied to this call's launches.  Results equal cp_als_sweep's.
+ *   EINVAL if max_n I_n * R > MTTKRP_STATIC_MBUF_FLOATS (before any work).
+ * All calls on one GPU share the array, and each leaves its contents behind
+ * (every MTTKRP output is fully written before it is read, so nothing needs
+ * clearing).  Calls that overlap in time on one GPU -- from different
+ * streams, threads or plans -- race on the array; calls on one stream are
+ * ordered.  Other arguments as in cp_als_sweep.
+ */
+#define MTTKRP_STATIC_MBUF_FLOATS 16777216
+mttkrp_status cp_als_sweep_static(mttkrp_plan_t p, void *const *d_factors,
+                                  mttkrp_dtype fdt, double *d_lambda, double *d_fit,
+                                  void *stream);
+
+/*
  * CP-ALS to convergence (Alg. "cp-als" with its loop): sweeps as in
  * cp_als_sweep until two consecutive fits differ by less than tol, or
  * max_sweeps sweeps.  The Gram matrices are computed once at the start and

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmttkrp.so")
 
 MAX_MODES = 8
 MAX_NNZ = (1 << 31) - (1 << 20)   # MTTKRP_MAX_NNZ
+STATIC_MBUF_FLOATS = 1 << 24      # MTTKRP_STATIC_MBUF_FLOATS
 OK, EINVAL, ERANGE, ENOMEM, ESTATE, EHIP = range(6)
 F32, BF16 = 0, 1
 NO_IMPLICIT_REMAP = 1
@@ -30,7 +31,8 @@ INFO_NSPLIT, INFO_G, INFO_M, INFO_RIDGE = 4, 5, 6, 7
 INFO_RECORD_BYTES = 8
 
 SYMBOLS = ["mttkrp_plan_workspace", "mttkrp_plan", "mttkrp_mode",
-           "mttkrp_all_modes", "remap", "cp_loss_grad", "cp_als_sweep", "cp_als",
+           "mttkrp_all_modes", "remap", "cp_loss_grad", "cp_als_sweep",
+           "cp_als_sweep_static", "cp_als",
            "mttkrp_plan_query", "mttkrp_plan_info", "mttkrp_profile",
            "mttkrp_profile_read", "mttkrp_plan_destroy", "mttkrp_status_str",
            "mttkrp_last_error"]
@@ -69,6 +71,7 @@ def load():
         "remap": [_vp, _int, _vp],
         "cp_loss_grad": [_vp, _vp, _int, _vp, _vp, _vp, _vp],
         "cp_als_sweep": [_vp, _vp, _int, _vp, _vp, _vp, _vp],
+        "cp_als_sweep_static": [_vp, _vp, _int, _vp, _vp, _vp],
         "cp_als": [_vp, _vp, _int, _vp, _vp, _int, ctypes.c_double, _vp,
                    ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double), _vp],
         "mttkrp_plan_query": [_vp, _int, _int, _vp, ctypes.c_size_t, _vp],
@@ -161,6 +164,12 @@ def cp_als_sweep(plan, d_factors, fdt, d_mbuf, d_lambda, d_fit, stream=0):
     lib = load()
     _check(lib.cp_als_sweep(plan, _ptrs(d_factors), fdt, d_mbuf, d_lambda,
                             d_fit or None, stream or None), plan)
+
+
+def cp_als_sweep_static(plan, d_factors, fdt, d_lambda, d_fit, stream=0):
+    lib = load()
+    _check(lib.cp_als_sweep_static(plan, _ptrs(d_factors), fdt, d_lambda, d_fit or None,
+                                   stream or None), plan)
 
 
 def cp_als(plan, d_factors, fdt, d_mbuf, d_lambda, max_sweeps, tol, d_fit_trace=0, stream=0):

@@ -137,6 +137,13 @@ class Plan:
                           _ptr(mbuf), _ptr(lam), _ptr(fit), _stream())
         return lam, fit
 
+    def cp_als_sweep_static(self, factors, lam, fit=None):
+        """One CP-ALS sweep whose scratch is the library's static device
+        array (no allocation in the call); `factors` are updated in place,
+        `lam` (FP64, R) and `fit` (FP64 scalar or None) are written."""
+        _abi.cp_als_sweep_static(self.handle, [_ptr(f) for f in factors], _fdt(factors),
+                                 _ptr(lam), _ptr(fit), _stream())
+
     def cp_als(self, factors, max_sweeps, tol=0.0, mbuf=None, lam=None, trace=True):
         """CP-ALS until two consecutive fits differ by less than `tol` (or
         `max_sweeps` sweeps); `factors` are updated in place.  Returns

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -942,6 +943,13 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
     }
     if (hipMemsetAsync(p->ridge(), 0, 8, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return bail(fail(p, MTTKRP_EHIP, "plan finish"));
+    // the side stream and its events exist from here on, so that no later
+    // call creates HIP objects
+    if (ensure_aux(p) != MTTKRP_OK) {
+        g_last_error = p->err;
+        mttkrp_plan_destroy(p);
+        return MTTKRP_EHIP;
+    }
     p->cur = 0;
     p->buf = 0;
     *out = p;
@@ -1169,6 +1177,71 @@ mttkrp_status cp_als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype
     hipLaunchKernelGGL(als::zero_i32, dim3(1), dim3(64), 0, s, p->ridge(), 2);
     HIPCHK(p, hipGetLastError());
     return als_sweep(p, d_factors, fdt, d_mbuf, d_lambda, d_fit, false, s);
+}
+
+}  // extern "C"
+
+// Scratch of cp_als_sweep_static: the MTTKRP output M_n of the sweep, one
+// array per GPU (each device holds its own copy of the module's globals),
+// kept until the process ends.  Host code never uses the array's name as an
+// address: its device address is looked up once per device below.
+static __device__ __align__(256) float scratch[MTTKRP_STATIC_MBUF_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+mttkrp_status static_scratch(mttkrp_plan_t p, float **out)
+{
+    int dev = -1;
+    HIPCHK(p, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(p, MTTKRP_EINVAL, "device ordinal beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(p, MTTKRP_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                            hipGetErrorString(e));
+        g_scratch[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return MTTKRP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mttkrp_status cp_als_sweep_static(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+                                  double *d_lambda, double *d_fit, void *stream)
+{
+    if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");
+    int64_t need = 0;
+    for (int n = 0; n < p->L.N; ++n) need = std::max<int64_t>(need, p->L.dims[n] * p->L.R);
+    if (need > MTTKRP_STATIC_MBUF_FLOATS)
+        return fail(p, MTTKRP_EINVAL,
+                    "max_n I_n * R = " + std::to_string((long long)need) +
+                        " exceeds the static scratch of " +
+                        std::to_string((long long)MTTKRP_STATIC_MBUF_FLOATS) +
+                        " floats; use cp_als_sweep with a caller buffer");
+    float *mbuf = nullptr;
+    mttkrp_status st = static_scratch(p, &mbuf);
+    if (st != MTTKRP_OK) return st;
+    st = als_args(p, d_factors, fdt, mbuf, d_lambda);
+    if (st != MTTKRP_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // kernel timing would create HIP events: suspended for this call
+    const bool prof = p->prof;
+    p->prof = false;
+    hipLaunchKernelGGL(als::zero_i32, dim3(1), dim3(64), 0, s, p->ridge(), 2);
+    st = hipGetLastError() == hipSuccess ? MTTKRP_OK : fail(p, MTTKRP_EHIP, "launch");
+    if (st == MTTKRP_OK) st = als_sweep(p, d_factors, fdt, mbuf, d_lambda, d_fit, false, s);
+    p->prof = prof;
+    return st;
 }
 
 mttkrp_status cp_als(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt, float *d_mbuf,

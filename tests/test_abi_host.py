@@ -143,6 +143,7 @@ def test_python_constants_match_header():
              "PROF_MTTKRP": _abi.PROF_MTTKRP, "PROF_REMAP": _abi.PROF_REMAP,
              "PROF_RESID": _abi.PROF_RESID, "PROF_LOSS": _abi.PROF_LOSS,
              "MAX_NNZ": _abi.MAX_NNZ, "MAX_MODES": _abi.MAX_MODES,
+             "STATIC_MBUF_FLOATS": _abi.STATIC_MBUF_FLOATS,
              "F32": _abi.F32, "BF16": _abi.BF16, "OK": _abi.OK, "EINVAL": _abi.EINVAL,
              "ERANGE": _abi.ERANGE, "ENOMEM": _abi.ENOMEM, "ESTATE": _abi.ESTATE,
              "EHIP": _abi.EHIP}
