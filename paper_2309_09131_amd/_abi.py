@@ -61,6 +61,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} not built; run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname as the system's;
+    # whichever is loaded first serves the whole process, so torch is loaded
+    # before the library resolves its HIP dependency
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "mttkrp_plan_workspace": [_int, _vp, _i64, _int, _vp, _vp],
