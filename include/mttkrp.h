@@ -173,7 +173,11 @@ mttkrp_status remap(mttkrp_plan_t p, int to_mode, void *stream);
  *   d_loss   device double or NULL.
  *   d_grads  host array of nmodes device pointers (I_k x R FP32) or NULL.
  * With gradients: N residual-MTTKRP passes with fused remap, ending in the
- * layout it started in.  Loss only: one pass, layout unchanged.
+ * layout it started in; with the loss as well, the first of them also sums
+ * the squared residuals (the same FP32 terms, FP64 accumulation and
+ * reduction order as the loss-only pass, so the same value), except under
+ * MTTKRP_FUSED_REMAP, which runs the loss pass first.  Loss only: one pass,
+ * layout unchanged.
  */
 mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors,
                            mttkrp_dtype fdt, double *d_loss, float *const *d_grads,

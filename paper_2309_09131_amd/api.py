@@ -170,26 +170,36 @@ class Plan:
 class CpLoss(torch.autograd.Function):
     """Sampled CP loss sum_e (x_e - sum_r prod_n A_n(c_n(e), r))^2.
 
-    forward(plan, *factors) -> float64 scalar; backward runs the N residual
-    MTTKRP passes of cp_loss_grad with the upstream gradient as scale.
+    forward(plan, *factors) -> float64 scalar.  When any factor needs a
+    gradient, the forward evaluates loss and gradients together (the first
+    residual pass of cp_loss_grad also yields the loss, so this costs N
+    passes instead of 1 + N) and backward scales the kept gradients by the
+    upstream gradient; otherwise the forward is the single loss pass.
     """
 
     @staticmethod
     def forward(ctx, plan: Plan, *factors):
-        ctx.plan = plan
-        ctx.save_for_backward(*factors)
-        loss, _ = plan.cp_loss_grad(list(factors), loss=True, grads=False)
+        ctx.dtypes = [f.dtype for f in factors]
+        if any(ctx.needs_input_grad[1:]):
+            loss, grads = plan.cp_loss_grad(list(factors), loss=True, grads=True)
+            ctx.grads = grads
+        else:
+            loss, _ = plan.cp_loss_grad(list(factors), loss=True, grads=False)
+            ctx.grads = None
         return loss
 
     @staticmethod
     def backward(ctx, g):
-        factors = ctx.saved_tensors
-        scale = g.detach().to(torch.float64).contiguous()
-        _, grads = ctx.plan.cp_loss_grad(list(factors), loss=False, grads=True,
-                                         grad_scale=scale)
+        grads = ctx.grads
+        ctx.grads = None
         out = [None]
-        for f, gr in zip(factors, grads):
-            out.append(gr.to(f.dtype) if ctx.needs_input_grad[len(out)] else None)
+        for gr in grads:
+            k = len(out)
+            if ctx.needs_input_grad[k]:
+                # FP32 gradients (as the MTTKRP outputs), in the factor's dtype
+                out.append((gr * g.detach().to(gr.dtype)).to(ctx.dtypes[k - 1]))
+            else:
+                out.append(None)
         return tuple(out)
 
 

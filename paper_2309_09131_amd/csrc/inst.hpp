@@ -58,6 +58,9 @@ hipError_t launch_one(const Args &a, int kind, unsigned grid, hipStream_t s)
     else if (kind == KIND_RESID)
         hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_RESID, false>),
                            dim3(grid), blk, 0, s, a);
+    else if (kind == KIND_RESID_LOSS && !a.rout)
+        hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_RESID_LOSS, false>),
+                           dim3(grid), blk, 0, s, a);
     else if (kind == KIND_LOSS)
         hipLaunchKernelGGL((mttkrp_kernel<NM, W, FT, LANES, V, STRIDED, KIND_LOSS, false>),
                            dim3(grid), blk, 0, s, a);

@@ -50,8 +50,10 @@ struct LaneCfg {
 };
 
 // KIND_GATHER: the MTTKRP kernel's loads without its segmented reduction
-// (measurement only; contiguous lane forms).
-enum Kind { KIND_MTTKRP = 0, KIND_RESID = 1, KIND_LOSS = 2, KIND_GATHER = 3 };
+// (measurement only; contiguous lane forms).  KIND_RESID_LOSS: the residual
+// pass that also sums the squared residuals (loss and gradient in one pass).
+enum Kind { KIND_MTTKRP = 0, KIND_RESID = 1, KIND_LOSS = 2, KIND_GATHER = 3,
+            KIND_RESID_LOSS = 4 };
 
 template <int N>
 hipError_t launch_mttkrp(const Args &a, int bf16, LaneCfg c, int kind, unsigned grid,

@@ -239,6 +239,9 @@ __device__ __forceinline__ float slot_sum(float v)
 //                value m_e = sum_r A_n(c_n(e), r) prod_{w != n} A_w(c_w(e), r)
 //   KIND_LOSS    loss forward: sum_e rho_e^2, one FP64 partial per shard
 //                (FP32 terms, FP64 accumulation); no output rows
+//   KIND_RESID_LOSS  KIND_RESID that also writes KIND_LOSS's partials (the
+//                same terms in the same order), so a loss-and-gradient
+//                evaluation needs no separate loss pass
 //   KIND_GATHER  measurement only: the same record loads, factor-row
 //                gathers, row reuse and products, but every product is added
 //                into one register per lane and stored to the shard's first
@@ -254,7 +257,8 @@ __device__ __forceinline__ float slot_sum(float v)
 template <int N, int W, typename FT, int LANES, int V, bool STRIDED, int KIND, bool FUSE>
 __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 {
-    constexpr bool RESID = KIND == KIND_RESID;
+    constexpr bool RLOSS = KIND == KIND_RESID_LOSS;
+    constexpr bool RESID = KIND == KIND_RESID || RLOSS;
     constexpr bool LOSS = KIND == KIND_LOSS;
     constexpr bool GONLY = KIND == KIND_GATHER;
     constexpr bool MODEL = RESID || LOSS;        // m_e needed: output row gathered too
@@ -481,7 +485,13 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             if constexpr (RESID) {
                 // model value m_e (lanes outside the rank range hold 0)
                 const float m = slot_sum<LANES>(mm[u]);
-                if (ok[u]) c = coef * (__uint_as_float(rc[u].w[W]) - m);
+                if (ok[u]) {
+                    const float rho = __uint_as_float(rc[u].w[W]) - m;
+                    c = coef * rho;
+                    if constexpr (RLOSS) {
+                        if (sub == 0) lacc += (double)(rho * rho);   // as KIND_LOSS
+                    }
+                }
             } else {
                 if (ok[u]) c = __uint_as_float(rc[u].w[W]);
             }
@@ -520,6 +530,10 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     if constexpr (GONLY) {
         if (ract) store_row<V, STRIDED>(out + (int64_t)f * R, R, sub, acc);
         return;
+    }
+    if constexpr (RLOSS) {
+        lacc = wave_sum_d(lacc);                 // every lane takes part
+        if (lane == 0) a.partial[shard] = lacc;
     }
     const bool single = in_head;                 // whole run is one row
     const int tail_row = cur_row;

@@ -718,8 +718,8 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
                                       "(BF16) and 16-byte aligned factors");
     const int wpb = mk::MTT_WAVES;   // shards (waves) per workgroup
     const unsigned grid = (unsigned)((p->nshards[n] + wpb - 1) / wpb);
-    const int pk = kind == mk::KIND_MTTKRP  ? MTTKRP_PROF_MTTKRP
-                   : kind == mk::KIND_RESID ? MTTKRP_PROF_RESID
+    const int pk = kind == mk::KIND_MTTKRP                                    ? MTTKRP_PROF_MTTKRP
+                   : (kind == mk::KIND_RESID || kind == mk::KIND_RESID_LOSS) ? MTTKRP_PROF_RESID
                                             : MTTKRP_PROF_LOSS;
     ProfEvent ev{nullptr, nullptr, n, pk};
     const bool prof = p->prof;
@@ -1050,7 +1050,12 @@ mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp
             if (!d_grads[k]) return fail(p, MTTKRP_EINVAL, "gradient pointer is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Layout &L = p->L;
-    if (d_loss) {
+    // loss and gradients: the first residual pass also sums the squared
+    // residuals (identical terms, order and partials as the loss pass), so
+    // the loss costs no pass of its own; the in-kernel remap form keeps the
+    // separate loss pass
+    const bool joint = d_loss && d_grads && L.nnz > 0 && !(L.flags & MTTKRP_FUSED_REMAP);
+    if (d_loss && !joint) {
         if (L.nnz == 0) {
             HIPCHK(p, hipMemsetAsync(d_loss, 0, 8, s));
         } else {
@@ -1065,8 +1070,17 @@ mttkrp_status cp_loss_grad(mttkrp_plan_t p, const void *const *d_factors, mttkrp
         const int start = p->cur;
         for (int t = 0; t < L.N; ++t) {
             const int k = (start + t) % L.N;
-            st = run_pass(p, d_factors, fdt, d_grads[k], true, mk::KIND_RESID, d_grad_scale, s);
+            const bool with_loss = joint && t == 0;
+            st = run_pass(p, d_factors, fdt, d_grads[k], true,
+                          with_loss ? mk::KIND_RESID_LOSS : mk::KIND_RESID, d_grad_scale, s);
             if (st != MTTKRP_OK) return st;
+            if (with_loss) {
+                // the partials of mode k's shards; the remap that followed
+                // does not touch them
+                hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s,
+                                   p->rt<double>(L.rt_partial), p->nshards[k], d_loss);
+                HIPCHK(p, hipGetLastError());
+            }
         }
     }
     return join_aux(p, s);

@@ -69,6 +69,24 @@ def test_loss_and_gradient_match_oracle(case, flags):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
+@pytest.mark.parametrize("case", LOSS_CASES)
+def test_joint_loss_equals_loss_only_pass(case, flags):
+    """Loss and gradients together take the loss from the first residual
+    pass: the same value, bit for bit, as the loss pass alone, and the same
+    gradients as the gradient-only passes."""
+    t, p, facs = _loss_case(case, flags)
+    p.remap(len(t.dims) - 1)                 # start away from L_0
+    l_only, _ = p.cp_loss_grad(facs, grads=False)
+    l_joint, g_joint = p.cp_loss_grad(facs)
+    _, g_only = p.cp_loss_grad(facs, loss=False)
+    torch.cuda.synchronize()
+    assert p.cur_mode == len(t.dims) - 1
+    assert l_joint.item() == l_only.item(), (l_joint.item(), l_only.item())
+    for a, b in zip(g_joint, g_only):
+        assert torch.equal(a, b)
+
+
 def test_gpu_forward_central_difference_matches_gpu_gradient():
     """The loss is exactly quadratic in any single factor entry, so a large
     step (h = 0.25) swamps FP32 rounding without truncation error."""
@@ -106,6 +124,14 @@ def test_autograd_function_scales_by_upstream_gradient():
     fr2 = [facs[0].clone().requires_grad_(True), facs[1], facs[2]]
     cp_loss(p, fr2).backward()
     assert fr2[0].grad is not None
+    # no factor needs a gradient: the loss pass alone, the same value
+    with torch.no_grad():
+        l0 = cp_loss(p, facs)
+    assert not l0.requires_grad and l0.item() == loss.item()
+    # BF16 factors get BF16 gradients
+    fb = [f.clone().to(torch.bfloat16).requires_grad_(True) for f in facs]
+    cp_loss(p, fb).backward()
+    assert all(f.grad is not None and f.grad.dtype == torch.bfloat16 for f in fb)
 
 
 def test_loss_at_planted_truth_matches_noise_level():
@@ -317,7 +343,8 @@ def test_profile_events_count_every_kernel_launch():
     N = len(dims)
     p.profile(True)
     p.mttkrp_all_modes(facs)
-    p.cp_loss_grad(facs)
+    p.cp_loss_grad(facs)                    # loss from the first residual pass
+    p.cp_loss_grad(facs, grads=False)       # the loss pass alone
     torch.cuda.synchronize()
     for n in range(N):
         ms, c = p.profile_read(_abi.PROF_MTTKRP, n)
