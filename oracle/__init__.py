@@ -132,6 +132,21 @@ def remap_replay(dims, idx, l0=None):
     return layouts, perm, row_ptrs
 
 
+def locality_layouts(dims, idx):
+    """Layouts under the locality order (rows contiguous; inside a row the
+    Morton code of the two leading inputs, then the other inputs, then input
+    position) and their remap targets.  Returns (layouts (N+1, nnz), perm
+    (N, nnz))."""
+    lib = _load()
+    dims, idx = _dims(dims), _idx(idx)
+    N, nnz = idx.shape
+    layouts = np.empty((N + 1, nnz), dtype=np.int64)
+    perm = np.empty((N, nnz), dtype=np.int64)
+    _check(lib.oracle_locality_layouts(ctypes.c_int(N), _p(dims), ctypes.c_int64(nnz),
+                                       _p(idx), _p(layouts), _p(perm)), "locality_layouts")
+    return layouts, perm
+
+
 def shards(I, row_ptr, m, g):
     """Super-shard and shard tables for one mode."""
     lib = _load()

@@ -185,6 +185,93 @@ int oracle_remap_replay(int N, const int64_t *dims, int64_t nnz,
 }
 
 /* ------------------------------------------------------------------ */
+/* 2b. Locality order (Sec. V-J, preprocessing: Z-Morton ordering of the */
+/*    nonzeros).  Reading used for the plan option: each layout L_n keeps */
+/*    its output rows contiguous (c_n first) and orders the nonzeros of a */
+/*    row by the Morton code of its two leading inputs (c_{n-1}, c_{n-2}), */
+/*    then by the remaining inputs c_{n-3}, ..., c_{n+1}, then by input    */
+/*    position.  With two modes there is one input and the order is the   */
+/*    cyclic lexicographic one.  The remap still moves slot i of L_n to    */
+/*    the slot its element takes in L_{n+1}, now computed from the two     */
+/*    orders, since L_{n+1} is no longer a stable re-sort of L_n.          */
+/* ------------------------------------------------------------------ */
+
+/* Morton code of two 32-bit coordinates: bit k of a goes to bit 2k+1 and
+ * bit k of b to bit 2k, so a is the more significant one at every level. */
+static uint64_t morton2(uint32_t a, uint32_t b)
+{
+    uint64_t z = 0;
+    for (int k = 0; k < 32; ++k) {
+        z |= (uint64_t)((a >> k) & 1u) << (2 * k + 1);
+        z |= (uint64_t)((b >> k) & 1u) << (2 * k);
+    }
+    return z;
+}
+
+static int g_mode;
+
+static int32_t coord_of(int m, int64_t e) { return g_idx[(int64_t)m * g_nnz + e]; }
+
+static int cmp_locality(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    const int n = g_mode, N = g_N;
+    int32_t ca = coord_of(n, a), cb = coord_of(n, b);
+    if (ca != cb) return ca < cb ? -1 : 1;
+    int k0 = 1;                                   /* first input not yet compared */
+    if (N >= 3) {
+        const int m1 = (n + N - 1) % N, m2 = (n + N - 2) % N;
+        uint64_t za = morton2((uint32_t)coord_of(m1, a), (uint32_t)coord_of(m2, a));
+        uint64_t zb = morton2((uint32_t)coord_of(m1, b), (uint32_t)coord_of(m2, b));
+        if (za != zb) return za < zb ? -1 : 1;
+        k0 = 3;
+    }
+    for (int k = k0; k < N; ++k) {                /* c_{n-k}, k = k0 .. N-1 */
+        const int m = (n + N - k) % N;
+        ca = coord_of(m, a);
+        cb = coord_of(m, b);
+        if (ca != cb) return ca < cb ? -1 : 1;
+    }
+    return (a < b) ? -1 : (a > b);
+}
+
+/*
+ * Layouts and remap targets under the locality order.
+ *   layouts  (N+1) x nnz: layouts[n*nnz + j] = input position at slot j of
+ *            L_n; row N repeats L_0 (one sweep is a cycle).
+ *   perm     N x nnz: perm[n*nnz + i] = slot in L_{n+1} of the element at
+ *            slot i of L_n.
+ */
+int oracle_locality_layouts(int N, const int64_t *dims, int64_t nnz, const int32_t *idx,
+                            int64_t *layouts, int64_t *perm)
+{
+    if (N < 2 || N > ORACLE_MAX_MODES || nnz < 0) return -1;
+    for (int n = 0; n < N; ++n)
+        for (int64_t e = 0; e < nnz; ++e) {
+            int32_t c = idx[(int64_t)n * nnz + e];
+            if (c < 0 || c >= dims[n]) return -3;
+        }
+    g_N = N; g_nnz = nnz; g_idx = idx;
+    for (int n = 0; n < N; ++n) {
+        int64_t *ord = layouts + (int64_t)n * nnz;
+        for (int64_t j = 0; j < nnz; ++j) ord[j] = j;
+        g_mode = n;
+        qsort(ord, (size_t)nnz, sizeof(int64_t), cmp_locality);
+    }
+    memcpy(layouts + (int64_t)N * nnz, layouts, sizeof(int64_t) * (size_t)nnz);
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!slot) return -2;
+    for (int n = 0; n < N; ++n) {
+        const int64_t *cur = layouts + (int64_t)n * nnz;
+        const int64_t *next = layouts + (int64_t)(n + 1) * nnz;
+        for (int64_t j = 0; j < nnz; ++j) slot[next[j]] = j;     /* element -> slot */
+        for (int64_t i = 0; i < nnz; ++i) perm[(int64_t)n * nnz + i] = slot[cur[i]];
+    }
+    free(slot);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* 3. Partitions (Sec. III-A): mode-n indices cut into k_n sets of m_n   */
 /*    consecutive indices (last set short: k_n = ceil(I_n / m_n)); the   */
 /*    nonzeros incident on set j form super-shard SS_{n,j}; each         */

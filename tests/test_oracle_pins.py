@@ -163,6 +163,100 @@ def test_remap_replay_reaches_cyclic_lexicographic_layouts(dims, nnz, dups):
     assert np.array_equal(comp, np.arange(nnz))
 
 
+# ---------------------------------------------------------------- locality order
+def z_curve(k):
+    """The Z-order curve on a 2^k x 2^k grid by its recursive definition:
+    the four quadrants in the order (a_hi, b_hi) = (0,0), (0,1), (1,0),
+    (1,1), each traversed the same way (a is the more significant axis)."""
+    if k == 0:
+        return [(0, 0)]
+    h = 1 << (k - 1)
+    sub = z_curve(k - 1)
+    return [(ah * h + a, bh * h + b) for ah in (0, 1) for bh in (0, 1) for a, b in sub]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_locality_order_follows_the_z_curve_on_full_grids(k):
+    """One output row holding every point of a 2^k grid of its two leading
+    inputs, in shuffled input order: the oracle's locality layout visits
+    them along the Z curve.  Checked for output mode 0 of a 3-mode tensor
+    (inputs c_2 then c_1) and output mode 1 of a 4-mode tensor (inputs c_0
+    then c_3; c_2 is constant)."""
+    s = 1 << k
+    curve = z_curve(k)
+    rng = np.random.default_rng(k)
+    pts = np.array([(a, b) for a in range(s) for b in range(s)])
+    pts = pts[rng.permutation(len(pts))]
+    # 3 modes, output mode 0: c_{-1} = c_2 is the more significant input
+    idx = np.stack([np.zeros(len(pts)), pts[:, 1], pts[:, 0]]).astype(np.int32)
+    lay, _ = oracle.locality_layouts((1, s, s), idx)
+    got = [(int(idx[2][e]), int(idx[1][e])) for e in lay[0]]
+    assert got == curve
+    # 4 modes, output mode 1: inputs c_0 (more significant) then c_3
+    idx4 = np.stack([pts[:, 0], np.full(len(pts), 2), np.full(len(pts), 1),
+                     pts[:, 1]]).astype(np.int32)
+    lay4, _ = oracle.locality_layouts((s, 3, 2, s), idx4)
+    got4 = [(int(idx4[0][e]), int(idx4[3][e])) for e in lay4[1]]
+    assert got4 == curve
+
+
+def spread_bits(x):
+    """Bit k of a 32-bit value to bit 2k (mask-and-shift bit spreading)."""
+    x = x.astype(np.uint64) & np.uint64(0xFFFFFFFF)
+    for sh, m in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF),
+                  (4, 0x0F0F0F0F0F0F0F0F), (2, 0x3333333333333333),
+                  (1, 0x5555555555555555)):
+        x = (x | (x << np.uint64(sh))) & np.uint64(m)
+    return x
+
+
+def locality_lexsort(idx, n):
+    """(c_n, Z(c_{n-1}, c_{n-2}), c_{n-3}, ..., c_{n+1}, input position)."""
+    N, nnz = idx.shape
+    keys = [np.arange(nnz)]                       # least significant first
+    if N == 2:
+        keys += [idx[(n - 1) % N], idx[n]]
+        return np.lexsort(keys)
+    for k in range(N - 1, 2, -1):                 # c_{n+1} ... c_{n-3}
+        keys.append(idx[(n - k) % N])
+    z = (spread_bits(idx[(n - 1) % N]) << np.uint64(1)) | spread_bits(idx[(n - 2) % N])
+    keys += [z, idx[n]]
+    return np.lexsort(keys)
+
+
+@pytest.mark.parametrize("dims,nnz,dups", [((7, 5, 6), 120, True),
+                                            ((40, 30, 20), 3000, False),
+                                            ((4, 6, 3, 5), 200, False),
+                                            ((3, 2, 4, 2, 5), 150, True),
+                                            ((9, 8), 40, True),
+                                            ((70000, 90000, 5000), 4000, False)])
+def test_locality_layouts_invariants(dims, nnz, dups):
+    t = syn.random_tensor(dims, nnz, 2, seed=23, distinct=not dups)
+    N = len(dims)
+    lay, perm = oracle.locality_layouts(dims, t.idx)
+    _, _, rps = oracle.remap_replay(dims, t.idx)
+    for n in range(N):
+        assert np.array_equal(lay[n], locality_lexsort(t.idx, n)), n
+        # output rows contiguous in the same ranges as the canonical layout
+        c = t.idx[n][lay[n]]
+        assert np.all(np.diff(c) >= 0)
+        h = np.bincount(t.idx[n], minlength=dims[n])
+        assert np.array_equal(rps[n], np.concatenate([[0], np.cumsum(h)]))
+        # slot i of L_n goes to perm[i] of L_{n+1}
+        assert np.array_equal(np.sort(perm[n]), np.arange(nnz))
+        nxt = np.empty(nnz, np.int64)
+        nxt[perm[n]] = lay[n]
+        assert np.array_equal(nxt, lay[n + 1])
+    assert np.array_equal(lay[N], lay[0])
+    comp = np.arange(nnz)
+    for n in range(N):
+        comp = perm[n][comp]
+    assert np.array_equal(comp, np.arange(nnz))
+    if N == 2:                                    # one input: the canonical order
+        for n in range(N):
+            assert np.array_equal(lay[n], cyclic_lexsort(t.idx, n))
+
+
 # ---------------------------------------------------------------- shards / LPT
 def test_shard_tables_identities():
     t = syn.random_tensor((500, 40, 30), 6000, 2, seed=4, zipf_s=1.2)
