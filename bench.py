@@ -366,6 +366,30 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         del uplan
         log(f"unpacked-record fp32 sweep {unpacked_ms:.3f} ms")
 
+    locality = None
+    if args.locality:
+        # plan option: Morton order of the two leading inputs inside each
+        # output row (Sec. V-J preprocessing) instead of the lexicographic order
+        torch.cuda.synchronize()
+        t1 = time.time()
+        lplan = Plan(idx, vals, dims, R, g=args.g, flags=flags | _abi.LOCALITY_ORDER)
+        torch.cuda.synchronize()
+        lp_ms = (time.time() - t1) * 1e3
+        locality = {"plan_ms": round(lp_ms, 1)}
+        for name, F in (("fp32", f32), ("bf16", bf)):
+            lms = timer(lambda: lplan.mttkrp_all_modes(F, outs), args.steps, args.warmup)
+            lplan.profile(True)
+            timer(lambda: lplan.mttkrp_all_modes(F, outs), args.steps, 0)
+            lk = [lplan.profile_read(_abi.PROF_MTTKRP, n) for n in range(N)]
+            lr = [lplan.profile_read(_abi.PROF_REMAP, n) for n in range(N)]
+            lplan.profile(False)
+            locality[name] = {"sweep_ms": round(lms, 4),
+                              "mttkrp_kernel_ms": [round(m / max(c, 1), 4) for m, c in lk],
+                              "remap_kernel_ms": [round(m / max(c, 1), 4) for m, c in lr]}
+            log(f"locality order {name}: sweep {lms:.3f} ms; MTTKRP kernel ms "
+                f"{locality[name]['mttkrp_kernel_ms']}; remap {locality[name]['remap_kernel_ms']}")
+        del lplan
+
     als = None
     if args.config in (1, 5):
         als = {}
@@ -518,6 +542,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "bf16": result_bf16,
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
         "unpacked_records_sweep_ms": round(unpacked_ms, 4) if unpacked_ms else None,
+        "locality_order": locality,
         "layout_copy_per_mode_sweep_ms": round(ncopy_ms, 4),
         "cp_als": als,
         "sweep_ms_median": round(step_ms[len(step_ms) // 2], 4),
@@ -673,6 +698,30 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
         f"loss kernel {lossk[0] / lossk[1]:.4f} ms ({l_gbs:.0f} GB/s), remap "
         f"{remk[0] / max(remk[1], 1):.4f} ms")
 
+    locality = None
+    if args.locality:
+        # the same step on a plan with the Morton locality order
+        lplan = Plan(idx, vals, dims, R, g=args.g, flags=_abi.LOCALITY_ORDER)
+        torch.cuda.synchronize()
+
+        def lstep():
+            for f in fac:
+                f.grad = None
+            loss = cp_loss(lplan, fac)
+            loss.backward()
+            return loss
+
+        lms = timer(lstep, args.steps, args.warmup)
+        lplan.profile(True)
+        timer(lstep, args.steps, 0)
+        lres = [lplan.profile_read(_abi.PROF_RESID, n) for n in range(N)]
+        lplan.profile(False)
+        locality = {"step_ms": round(lms, 4),
+                    "residual_kernel_ms": [round(m / max(c, 1), 4) for m, c in lres]}
+        log(f"locality order: step {lms:.3f} ms; residual kernel ms "
+            f"{locality['residual_kernel_ms']}")
+        del lplan
+
     # checks on a 10K-nonzero subsample (first in generation order)
     S = 10_000
     sub_idx = np.ascontiguousarray(T.idx[:, :S])
@@ -766,6 +815,8 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
                         "model_bytes_per_launch": int(nnz * (E + N * R * 4)),
                         "model_GBs": round(l_gbs, 1)},
         "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
+        "residual_kernel_ms_per_mode": [round(m / max(c, 1), 4) for m, c in resid],
+        "locality_order": locality,
         "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "checks": checks,
     }
@@ -797,6 +848,8 @@ def main():
                     help="size of a plain device copy run for counter calibration")
     ap.add_argument("--rank-sweep", default="",
                     help="comma-separated ranks: sweep time against R on the same tensor")
+    ap.add_argument("--locality", action="store_true",
+                    help="also time a plan with the Morton locality order inside rows")
     ap.add_argument("--m-sweep", default="",
                     help="comma-separated super-shard sizes m (0 = default rule)")
     ap.add_argument("--g-sweep", default="",

@@ -91,6 +91,18 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
                                         Needs the contiguous lane forms (R a
                                         multiple of 4 for FP32, 8 for BF16). */
 
+#define MTTKRP_LOCALITY_ORDER 32u    /* plan option (Sec. V-J, Z-Morton
+                                        ordering at preprocessing): inside
+                                        each output row of L_n the nonzeros
+                                        follow the Morton code of their two
+                                        leading inputs (c_{n-1}, c_{n-2};
+                                        c_{n-1} the more significant), then
+                                        c_{n-3}, ..., c_{n+1}, then input
+                                        position, instead of the cyclic
+                                        lexicographic order; P_n is composed
+                                        from the two layouts.  Results are the
+                                        same sums in another order.         */
+
 /* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
 typedef struct {
     int32_t g;                       /* nonzeros per shard; default 1024     */

@@ -24,6 +24,7 @@ NATURAL_ORDER = 2
 FUSED_REMAP = 4
 UNPACKED_RECORDS = 8
 GATHER_ONLY = 16
+LOCALITY_ORDER = 32
 PROF_MTTKRP, PROF_REMAP, PROF_RESID, PROF_LOSS = 0, 1, 2, 3
 Q_LAYOUT, Q_PERM, Q_ROW_PTR, Q_SHARDS, Q_LPT = range(5)
 INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2

@@ -781,6 +781,89 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     return MTTKRP_OK;
 }
 
+// Locality order (MTTKRP_LOCALITY_ORDER; Sec. V-J, Z-Morton ordering at
+// preprocessing): out = input positions in L_n order, L_n keyed by (c_n,
+// Morton(c_{n-1}, c_{n-2}), c_{n-3}, ..., c_{n+1}, input position); with two
+// modes (c_n, c_{n-1}, position).  Stable LSD radix passes, least
+// significant key first; the Morton code in 31-bit slices.
+static mttkrp_status sort_locality(mttkrp_plan_t p, const int32_t *d_idx, int n, int32_t *out,
+                                   hipStream_t s)
+{
+    const Layout &L = p->L;
+    const int N = L.N;
+    const int64_t nnz = L.nnz;
+    int32_t *kb[2] = {p->rt<int32_t>(L.ps_k0), p->rt<int32_t>(L.ps_k1)};
+    int32_t *vb[2] = {p->rt<int32_t>(L.ps_v0), p->rt<int32_t>(L.ps_v1)};
+    const unsigned gg = grid_for(nnz);
+    const int32_t *src = nullptr;
+    // one stable pass over the keys the launch wrote into (kb[0], vb[0])
+    auto pass = [&](int bits) -> mttkrp_status {
+        HIPCHK(p, hipGetLastError());
+        int which = 0;
+        mttkrp_status st = radix_sort(p, kb[0], vb[0], kb[1], vb[1], nnz, bits, s, &which);
+        if (st != MTTKRP_OK) return st;
+        HIPCHK(p, hipMemcpyAsync(out, vb[which], nnz * 4, hipMemcpyDeviceToDevice, s));
+        src = out;
+        return MTTKRP_OK;
+    };
+    auto coord_pass = [&](int w) -> mttkrp_status {
+        hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + w * nnz,
+                           src, nnz, kb[0], vb[0], 0);
+        return pass(key_bits(L.dims[w]));
+    };
+    mttkrp_status st;
+    if (N == 2) {
+        if ((st = coord_pass((n + 1) % N)) != MTTKRP_OK) return st;
+    } else {
+        for (int k = N - 1; k >= 3; --k)               // c_{n+1}, ..., c_{n-3}
+            if ((st = coord_pass((n + N - k) % N)) != MTTKRP_OK) return st;
+        const int m1 = (n + N - 1) % N, m2 = (n + N - 2) % N;
+        const int zb = 2 * std::max(key_bits(L.dims[m1]), key_bits(L.dims[m2]));
+        for (int shift = 0; shift < std::max(zb, 1); shift += 31) {
+            hipLaunchKernelGGL(plan::morton_keys_kernel, dim3(gg), dim3(256), 0, s,
+                               d_idx + m1 * nnz, d_idx + m2 * nnz, src, nnz, shift, kb[0], vb[0]);
+            if ((st = pass(std::min(31, zb - shift))) != MTTKRP_OK) return st;
+        }
+    }
+    return coord_pass(n);                              // c_n, most significant
+}
+
+// Plan steps 2-3 under the locality order: L_0's records, and per mode the
+// row pointers of L_n and P_n[i] = slot in L_{n+1} of the element at slot i
+// of L_n (composed from the two orders).
+static mttkrp_status plan_locality(mttkrp_plan_t p, const int32_t *d_idx, const float *d_vals,
+                                   hipStream_t s)
+{
+    const Layout &L = p->L;
+    const int N = L.N;
+    const int64_t nnz = L.nnz;
+    int32_t *kb[2] = {p->rt<int32_t>(L.ps_k0), p->rt<int32_t>(L.ps_k1)};
+    int32_t *vb1 = p->rt<int32_t>(L.ps_v1);
+    int32_t *ob[2] = {p->rt<int32_t>(L.ps_o0), p->rt<int32_t>(L.ps_o1)};
+    const unsigned gg = grid_for(nnz);
+    mttkrp_status st = sort_locality(p, d_idx, 0, ob[0], s);
+    if (st != MTTKRP_OK) return st;
+    HIPCHK(p, launch_pack_any(L, d_idx, d_vals, ob[0], p->rec(0), s));
+    int oc = 0;
+    for (int n = 0; n < N; ++n) {
+        const int nx = (n + 1) % N;
+        // c_n in layout order -> row pointers of L_n
+        hipLaunchKernelGGL(plan::gather_keys_kernel, dim3(gg), dim3(256), 0, s, d_idx + n * nnz,
+                           ob[oc], nnz, kb[1], vb1, 1);
+        hipLaunchKernelGGL(plan::row_ptr_kernel, dim3(grid_for(L.dims[n] + 1)), dim3(256), 0, s,
+                           kb[1], nnz, (int32_t)L.dims[n], p->rp(n));
+        HIPCHK(p, hipGetLastError());
+        if ((st = sort_locality(p, d_idx, nx, ob[oc ^ 1], s)) != MTTKRP_OK) return st;
+        hipLaunchKernelGGL(plan::slot_of_kernel, dim3(gg), dim3(256), 0, s, ob[oc ^ 1], nnz,
+                           kb[0]);
+        hipLaunchKernelGGL(plan::compose_kernel, dim3(gg), dim3(256), 0, s, kb[0], ob[oc], nnz,
+                           p->perm(n));
+        HIPCHK(p, hipGetLastError());
+        oc ^= 1;
+    }
+    return MTTKRP_OK;
+}
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -873,6 +956,10 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
     int32_t *vb[2] = {p->rt<int32_t>(L.ps_v0), p->rt<int32_t>(L.ps_v1)};
     int32_t *ob[2] = {p->rt<int32_t>(L.ps_o0), p->rt<int32_t>(L.ps_o1)};
     const unsigned gg = grid_for(nnz);
+    if (L.flags & MTTKRP_LOCALITY_ORDER) {
+        st = plan_locality(p, d_idx, d_vals, s);
+        if (st != MTTKRP_OK) return bail(st);
+    } else {
     // 2. L_0: stable LSD sort of input positions by c_1, c_2, ..., c_{N-1}, c_0
     const int32_t *src = nullptr;
     for (int t = 1; t <= N; ++t) {
@@ -907,6 +994,7 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
                            p->perm(n), ob[oc], ob[oc ^ 1]);
         if (hipGetLastError() != hipSuccess) return bail(fail(p, MTTKRP_EHIP, "plan kernels"));
         oc ^= 1;
+    }
     }
     // ||X||^2 for the fit
     {

@@ -248,6 +248,51 @@ __global__ void invert_kernel(const int32_t *__restrict__ q, int64_t n, int32_t 
     }
 }
 
+// Locality order (plan option): a 31-bit slice, from bit `shift`, of the
+// Morton code of two coordinates (bit k of a at bit 2k+1, of b at bit 2k)
+// of input src[j] (or j), as a radix-sort key; vals[j] = that input.
+__device__ __forceinline__ uint64_t spread_even(uint32_t x)
+{
+    uint64_t v = x;
+    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+}
+
+__global__ void morton_keys_kernel(const int32_t *__restrict__ ca, const int32_t *__restrict__ cb,
+                                   const int32_t *__restrict__ src, int64_t n, int shift,
+                                   int32_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = src ? src[j] : (int32_t)j;
+        const uint64_t z = (spread_even((uint32_t)ca[s]) << 1) | spread_even((uint32_t)cb[s]);
+        keys[j] = (int32_t)((z >> shift) & 0x7fffffffull);
+        vals[j] = s;
+    }
+}
+
+// slot[ord[j]] = j: the position of each input in a layout.
+__global__ void slot_of_kernel(const int32_t *__restrict__ ord, int64_t n,
+                               int32_t *__restrict__ slot)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        slot[ord[j]] = (int32_t)j;
+}
+
+// P[i] = slot[ord[i]]: the slot, in the next layout, of slot i's element.
+__global__ void compose_kernel(const int32_t *__restrict__ slot, const int32_t *__restrict__ ord,
+                               int64_t n, int32_t *__restrict__ P)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        P[i] = slot[ord[i]];
+}
+
 // Row pointers of a layout sorted by the mode's coordinate: row_ptr[r] =
 // first position whose coordinate is >= r (= number of nonzeros with
 // coordinate < r), r = 0..I, by a binary search of the coordinates in

@@ -133,7 +133,7 @@ def test_python_constants_match_header():
                  for m in re.finditer(r"\bMTTKRP_([A-Z_0-9]+)\s*=\s*(\d+)", src)})
     pairs = {"NO_IMPLICIT_REMAP": _abi.NO_IMPLICIT_REMAP, "NATURAL_ORDER": _abi.NATURAL_ORDER,
              "FUSED_REMAP": _abi.FUSED_REMAP, "UNPACKED_RECORDS": _abi.UNPACKED_RECORDS,
-             "GATHER_ONLY": _abi.GATHER_ONLY,
+             "GATHER_ONLY": _abi.GATHER_ONLY, "LOCALITY_ORDER": _abi.LOCALITY_ORDER,
              "Q_LAYOUT": _abi.Q_LAYOUT, "Q_PERM": _abi.Q_PERM, "Q_ROW_PTR": _abi.Q_ROW_PTR,
              "Q_SHARDS": _abi.Q_SHARDS, "Q_LPT": _abi.Q_LPT,
              "INFO_CUR_MODE": _abi.INFO_CUR_MODE, "INFO_NSHARDS": _abi.INFO_NSHARDS,

@@ -44,7 +44,7 @@ def _grad_ref(t, facs64):
     return refs
 
 
-@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP])
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP, _abi.LOCALITY_ORDER])
 @pytest.mark.parametrize("case", LOSS_CASES)
 def test_loss_and_gradient_match_oracle(case, flags):
     say("loss case", case, "flags", flags)

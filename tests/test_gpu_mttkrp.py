@@ -56,6 +56,33 @@ def test_plan_tables_bit_exact(case):
                               oracle_layout_records(t, layouts[n])), n
 
 
+# Morton codes wider than 31 bits: sorted in two slices
+LOCALITY_CASES = PLAN_CASES + [((300000, 200000, 5000), 5000, 4, 31, True, 0.0, 64),
+                               ((70000, 90000, 5000, 300), 6000, 4, 32, True, 1.1, 128)]
+
+
+@pytest.mark.parametrize("case", LOCALITY_CASES)
+def test_locality_order_plan_bit_exact(case):
+    """The locality-order option: every layout, remap target and row pointer
+    equal the oracle's (Morton order inside output rows), byte for byte,
+    through a whole sweep of standalone remaps."""
+    dims, nnz, R, seed, distinct, zipf, g = case
+    say("locality plan case", case)
+    t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
+    p, _ = make_plan(t, g=g, workers=4, flags=_abi.LOCALITY_ORDER)
+    layouts, perm = oracle.locality_layouts(dims, t.idx)
+    _, _, rps = oracle.remap_replay(dims, t.idx)
+    N = len(dims)
+    for n in range(N):
+        assert np.array_equal(p.query(_abi.Q_PERM, n), perm[n]), n
+        assert np.array_equal(p.query(_abi.Q_ROW_PTR, n), rps[n]), n
+    for n in range(N + 1):
+        if n:
+            p.remap(n % N)
+        assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                              oracle_layout_records(t, layouts[n])), n
+
+
 MTT_CASES = [
     # dims, nnz, R, seed, distinct, zipf, g, factor dtype
     ((60, 50, 40), 3000, 16, 11, True, 0.0, 64),
@@ -84,7 +111,8 @@ def _oracle_all(t, facs64):
             for n in range(len(t.dims))]
 
 
-@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP, _abi.UNPACKED_RECORDS])
+@pytest.mark.parametrize("flags", [0, _abi.FUSED_REMAP, _abi.UNPACKED_RECORDS,
+                                   _abi.LOCALITY_ORDER])
 @pytest.mark.parametrize("case", MTT_CASES)
 def test_mttkrp_all_modes_fp32(case, flags):
     dims, nnz, R, seed, distinct, zipf, g = case
@@ -102,8 +130,9 @@ def test_mttkrp_all_modes_fp32(case, flags):
     for a, b in zip(outs, outs2):
         assert torch.equal(a, b)
     # the layout is back in L_0 and byte-identical to the oracle's
-    assert np.array_equal(p.query(_abi.Q_LAYOUT),
-                          oracle_layout_records(t, oracle.canonical_order(t.idx)))
+    l0 = (oracle.locality_layouts(dims, t.idx)[0][0] if flags & _abi.LOCALITY_ORDER
+          else oracle.canonical_order(t.idx))
+    assert np.array_equal(p.query(_abi.Q_LAYOUT), oracle_layout_records(t, l0))
 
 
 @pytest.mark.parametrize("case", [c for c in MTT_CASES if c[2] % 8 == 0 or c[2] in (1, 17, 20, 12)])
