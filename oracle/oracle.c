@@ -94,6 +94,14 @@ int oracle_mttkrp_rows(int N, const int64_t *dims, int64_t nnz,
             if (out_abs) out_abs[k * R + r] += pa;
         }
     }
+    /* a row listed more than once was summed into the slot of its last
+     * listing; every listing gets the row */
+    for (int64_t k = 0; k < nrows; ++k) {
+        const int64_t k0 = slot[rows[k]];
+        if (k0 == k) continue;
+        memcpy(out + k * R, out + k0 * R, sizeof(double) * (size_t)R);
+        if (out_abs) memcpy(out_abs + k * R, out_abs + k0 * R, sizeof(double) * (size_t)R);
+    }
     free(slot);
     return 0;
 }

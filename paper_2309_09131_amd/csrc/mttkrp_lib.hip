@@ -30,6 +30,18 @@ int seg_block(int R) { return std::min(256, SEG_VALS / R); }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The integer a C caller passed for an enum parameter, read without an
+// enum-typed load (C allows any int there; C++ makes loading a value outside
+// the enumeration undefined), so it can be validated first.
+template <typename E>
+int raw_enum(const E &e)
+{
+    static_assert(sizeof(E) == sizeof(int), "C enums are int-sized here");
+    int v;
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
 struct Layout {
     int N;
     int64_t dims[MTTKRP_MAX_MODES];
@@ -588,10 +600,11 @@ static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
 }
 
 static mttkrp_status check_factors(mttkrp_plan_t p, const void *const *f, int skip_ok, int mode,
-                                   mttkrp_dtype fdt)
+                                   const mttkrp_dtype &fdt)
 {
     if (!f) return fail(p, MTTKRP_EINVAL, "factor pointer array is NULL");
-    if (fdt != MTTKRP_F32 && fdt != MTTKRP_BF16) return fail(p, MTTKRP_EINVAL, "bad dtype");
+    const int dt = raw_enum(fdt);               // validated before any enum use
+    if (dt != MTTKRP_F32 && dt != MTTKRP_BF16) return fail(p, MTTKRP_EINVAL, "bad dtype");
     for (int w = 0; w < p->L.N; ++w)
         if (!f[w] && !(skip_ok && w == mode))
             return fail(p, MTTKRP_EINVAL, "factor pointer is NULL for mode " + std::to_string(w));
@@ -869,7 +882,7 @@ extern "C" {
 
 const char *mttkrp_status_str(mttkrp_status st)
 {
-    switch (st) {
+    switch (raw_enum(st)) {
     case MTTKRP_OK: return "ok";
     case MTTKRP_EINVAL: return "invalid argument";
     case MTTKRP_ERANGE: return "coordinate out of range";
@@ -1260,7 +1273,7 @@ static mttkrp_status als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_d
     return MTTKRP_OK;
 }
 
-static mttkrp_status als_args(mttkrp_plan_t p, void *const *d_factors, mttkrp_dtype fdt,
+static mttkrp_status als_args(mttkrp_plan_t p, void *const *d_factors, const mttkrp_dtype &fdt,
                               float *d_mbuf, double *d_lambda)
 {
     if (!p) return fail(nullptr, MTTKRP_EINVAL, "plan is NULL");

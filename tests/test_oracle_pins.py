@@ -114,7 +114,7 @@ def test_mttkrp_abs_scale_and_row_subset():
     X = dense_from_coo(dims, t.idx, t.vals)
     ref_abs = mttkrp_einsum(np.abs(X), [np.abs(f) for f in t.factors], 1)
     assert np.allclose(fabs, ref_abs, rtol=1e-13)
-    rows = np.array([0, 7, 29, 3])
+    rows = np.array([0, 7, 29, 3, 7, 0])          # rows may repeat
     sub, sabs = oracle.mttkrp_rows(dims, t.idx, t.vals, t.factors, 1, rows)
     assert np.allclose(sub, full[rows], rtol=1e-13, atol=1e-13)
     assert np.allclose(sabs, fabs[rows], rtol=1e-13)
