@@ -854,6 +854,10 @@ def main():
                     help="comma-separated super-shard sizes m (0 = default rule)")
     ap.add_argument("--g-sweep", default="",
                     help="comma-separated shard sizes g: plan and sweep time against g")
+    ap.add_argument("--no-loss-workload", action="store_true",
+                    help="with the default workload, skip the sampled-loss workload "
+                         "(50M nonzeros, R = 64) whose forward + backward step is "
+                         "reported in a block of the same line")
     ap.add_argument("--als-recovery", type=int, default=0, metavar="D",
                     help="after the main run: CP-ALS to convergence on a fully stored "
                          "planted rank-16 D x D x D tensor (D = 368: 49.8M nonzeros)")
@@ -879,6 +883,20 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         rec = fn(args, torch, dev, syn, _abi, Plan, oracle)
+        if args.config == 3 and not args.no_loss_workload:
+            # the differentiation form on its own workload, in the same line:
+            # loss + gradient step, residual-kernel roofline, oracle checks
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            largs = argparse.Namespace(**vars(args))
+            largs.no_cpu_baseline = True
+            largs.locality = False
+            largs.copy_calib_mb = 0
+            lrec = bench_loss(largs, torch, dev, syn, _abi, Plan, oracle)
+            rec["loss_workload"] = {
+                k: lrec[k] for k in ("config", "ms_per_step", "value", "unit", "value_is",
+                                     "forward_ms", "residual_kernel_ms_per_mode",
+                                     "loss_kernel", "roofline", "checks")}
         if args.als_recovery > 0:
             rec["cp_als_recovery"] = als_recovery(torch, dev, Plan, args.als_recovery)
     print(json.dumps(rec), flush=True)
