@@ -698,6 +698,27 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
         f"loss kernel {lossk[0] / lossk[1]:.4f} ms ({l_gbs:.0f} GB/s), remap "
         f"{remk[0] / max(remk[1], 1):.4f} ms")
 
+    # the same step with BF16-stored factors (FP32 arithmetic); errors on the
+    # subsample below
+    bfac = [f.detach().to(torch.bfloat16).requires_grad_(True) for f in fac]
+
+    def bstep():
+        for f in bfac:
+            f.grad = None
+        loss = cp_loss(plan, bfac)
+        loss.backward()
+        return loss
+
+    bf_ms = timer(bstep, args.steps, args.warmup)
+    plan.profile(True)
+    timer(bstep, args.steps, 0)
+    bres = [plan.profile_read(_abi.PROF_RESID, n) for n in range(N)]
+    plan.profile_read(_abi.PROF_REMAP)
+    plan.profile(False)
+    del bfac
+    log(f"bf16 loss fwd+bwd {bf_ms:.3f} ms (x{ms / bf_ms:.2f}); residual kernel ms "
+        f"{[round(m / max(c, 1), 4) for m, c in bres]}")
+
     locality = None
     if args.locality:
         # the same step on a plan with the Morton locality order
@@ -757,6 +778,23 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
         fdo = (oracle.cp_loss_grad(dims, sub_idx, sub_val, hp, want_grad=False)
                - oracle.cp_loss_grad(dims, sub_idx, sub_val, hm, want_grad=False)) / 2e-3
         fd_orc.append(abs(fdo - G_ref[k][i, r]) / max(1.0, abs(G_ref[k][i, r])))
+    # BF16-stored factors on the subsample: against the oracle at the
+    # BF16-rounded factors (accumulation error) and at the FP32 factors
+    # (storage + accumulation)
+    sb = [f.to(torch.bfloat16) for f in sf]
+    lb, gb = sp.cp_loss_grad(sb)
+    rb64 = [f.float().cpu().numpy().astype(np.float64) for f in sb]
+    Lb_ref, Gb_ref = oracle.cp_loss_grad(dims, sub_idx, sub_val, rb64)
+    bf16_checks = {
+        "loss_rel_err_vs_oracle_bf16_factors": abs(lb.item() - Lb_ref) / abs(Lb_ref),
+        "grad_normwise_rel_err_vs_oracle_bf16_factors": max(
+            float(np.linalg.norm(gb[k].cpu().numpy() - Gb_ref[k]) / np.linalg.norm(Gb_ref[k]))
+            for k in range(N)),
+        "loss_rel_err_vs_oracle_fp32_factors": abs(lb.item() - L_ref) / abs(L_ref),
+        "grad_normwise_rel_err_vs_oracle_fp32_factors": max(
+            float(np.linalg.norm(gb[k].cpu().numpy() - G_ref[k]) / np.linalg.norm(G_ref[k]))
+            for k in range(N))}
+    log(f"bf16 checks {bf16_checks}")
     # loss at the planted truth: expected nnz * sigma^2
     truth = [torch.from_numpy(T.extra[f"true{n}"]).to(dev) for n in range(N)]
     l_true = plan.cp_loss_grad(truth, grads=False)[0].item()
@@ -816,6 +854,9 @@ def bench_loss(args, torch, dev, syn, _abi, Plan, oracle):
                         "model_GBs": round(l_gbs, 1)},
         "cpu_baseline": cpu, "forward_ms": round(fwd_ms, 4),
         "residual_kernel_ms_per_mode": [round(m / max(c, 1), 4) for m, c in resid],
+        "bf16": {"ms_per_step": round(bf_ms, 4), "speedup_vs_fp32": round(ms / bf_ms, 3),
+                 "residual_kernel_ms_per_mode": [round(m / max(c, 1), 4) for m, c in bres],
+                 "checks": bf16_checks, "tolerance": 2e-2},
         "locality_order": locality,
         "device_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "checks": checks,
@@ -896,7 +937,7 @@ def main():
             rec["loss_workload"] = {
                 k: lrec[k] for k in ("config", "ms_per_step", "value", "unit", "value_is",
                                      "forward_ms", "residual_kernel_ms_per_mode",
-                                     "loss_kernel", "roofline", "checks")}
+                                     "loss_kernel", "roofline", "checks", "bf16")}
         if args.als_recovery > 0:
             rec["cp_als_recovery"] = als_recovery(torch, dev, Plan, args.als_recovery)
     print(json.dumps(rec), flush=True)
