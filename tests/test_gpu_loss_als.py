@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 LOSS_CASES = [((60, 50, 40), 4000, 16, 51, 64), ((40, 3, 30, 5), 2500, 32, 52, 100),
               ((200, 150, 100), 20000, 64, 53, 256), ((30, 25, 20), 1000, 17, 54, 64),
-              ((9, 2, 11, 3, 4), 900, 8, 55, 32)]
+              ((9, 2, 11, 3, 4), 900, 8, 55, 32), ((300, 200), 6000, 32, 56, 128),
+              ((3, 2, 2, 3, 2, 2, 3, 2), 600, 8, 57, 50)]
 
 
 def _loss_case(case, flags=0):
