@@ -201,6 +201,7 @@ struct mttkrp_plan_s {
     // remap kernel; carry buffers alternate between consecutive passes
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_seg[2] = {nullptr, nullptr};
+    hipEvent_t ev_als = nullptr;   // CP-ALS: mode update forked after its MTTKRP
     bool seg_pending[2] = {false, false};
     // output range each pending reduction writes (callers may pass one
     // buffer for several passes: a later pass must not start before it)
@@ -654,6 +655,7 @@ static mttkrp_status ensure_aux(mttkrp_plan_t p)
     HIPCHK(p, hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
     HIPCHK(p, hipEventCreateWithFlags(&p->ev_seg[0], hipEventDisableTiming));
     HIPCHK(p, hipEventCreateWithFlags(&p->ev_seg[1], hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->ev_als, hipEventDisableTiming));
     return MTTKRP_OK;
 }
 
@@ -1068,7 +1070,7 @@ mttkrp_status mttkrp_plan_destroy(mttkrp_plan_t p)
     if (p->aux) {
         (void)hipStreamSynchronize(p->aux);
         (void)hipStreamDestroy(p->aux);
-        for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_seg[0], p->ev_seg[1]})
+        for (hipEvent_t e : {p->ev_fork, p->ev_join, p->ev_seg[0], p->ev_seg[1], p->ev_als})
             if (e) (void)hipEventDestroy(e);
     }
     delete p;
@@ -1202,19 +1204,19 @@ static mttkrp_status als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_d
     double *gpart = p->rt<double>(L.rt_gpart);
     const int tiles = (R + als::GRAM_TILE - 1) / als::GRAM_TILE;
     const int gbmax = std::max(1, GRAM_TARGET_BLOCKS / (tiles * tiles));
-    auto gram = [&](int w) -> mttkrp_status {
+    auto gram = [&](int w, hipStream_t gs) -> mttkrp_status {
         const int64_t I = L.dims[w];
         // at least 256 rows per block
         const int gb = (int)std::max<int64_t>(1, std::min<int64_t>(gbmax, (I + 255) / 256));
         const int64_t chunk = (I + gb - 1) / gb;
         const dim3 grid(gb, tiles, tiles), blk(256);
         if (bf)
-            hipLaunchKernelGGL(als::gram_partial<uint16_t>, grid, blk, 0, s,
+            hipLaunchKernelGGL(als::gram_partial<uint16_t>, grid, blk, 0, gs,
                                (const uint16_t *)d_factors[w], I, R, chunk, gpart);
         else
-            hipLaunchKernelGGL(als::gram_partial<float>, grid, blk, 0, s,
+            hipLaunchKernelGGL(als::gram_partial<float>, grid, blk, 0, gs,
                                (const float *)d_factors[w], I, R, chunk, gpart);
-        hipLaunchKernelGGL(als::gram_reduce, dim3(R * R), dim3(64), 0, s, gpart, gb, R,
+        hipLaunchKernelGGL(als::gram_reduce, dim3(R * R), dim3(64), 0, gs, gpart, gb, R,
                            G + (int64_t)w * R * R);
         HIPCHK(p, hipGetLastError());
         return MTTKRP_OK;
@@ -1226,37 +1228,62 @@ static mttkrp_status als_sweep(mttkrp_plan_t p, void *const *d_factors, mttkrp_d
     if (st != MTTKRP_OK) return st;
     if (!grams_valid)
         for (int w = 0; w < N; ++w)
-            if ((st = gram(w)) != MTTKRP_OK) return st;
+            if ((st = gram(w, s)) != MTTKRP_OK) return st;
     const int RT = std::min(256, next_pow2(R));
     double *colsq = p->rt<double>(L.rt_colsq);
+    // The update of A_n needs M_n (the MTTKRP and the split-row reduction on
+    // the side stream) but not the remap that follows the MTTKRP, and the
+    // remap needs nothing from the update.  So the update runs on the side
+    // stream, after the reduction, while the remap runs on `s`; the next
+    // MTTKRP, which reads A_n and overwrites M_n, waits for both.  (With the
+    // remap inside the MTTKRP kernel there is nothing to overlap: everything
+    // stays on `s`.)  Each kernel does the same work in the same order
+    // either way, so the results are identical.
+    const bool overlap = !(L.flags & MTTKRP_FUSED_REMAP);
+    hipStream_t as = overlap ? p->aux : s;
     for (int n = 0; n < N; ++n) {
-        st = run_pass(p, (const void *const *)d_factors, fdt, d_mbuf, true, mk::KIND_MTTKRP,
-                      nullptr, s);
+        if ((st = join_aux(p, s)) != MTTKRP_OK) return st;      // A_{n-1} stored
+        st = run_pass(p, (const void *const *)d_factors, fdt, d_mbuf, !overlap,
+                      mk::KIND_MTTKRP, nullptr, s);
         if (st != MTTKRP_OK) return st;
-        if ((st = join_aux(p, s)) != MTTKRP_OK) return st;      // M_n complete on s
-        hipLaunchKernelGGL(als::chol_inverse, dim3(1), dim3(256), 0, s, G, N, n, R,
+        if (overlap) {
+            // the side stream: after this MTTKRP (and, in stream order, after
+            // its split-row reduction) -> M_n complete there
+            HIPCHK(p, hipEventRecord(p->ev_als, s));
+            HIPCHK(p, hipStreamWaitEvent(p->aux, p->ev_als, 0));
+        } else if ((st = join_aux(p, s)) != MTTKRP_OK) {
+            return st;                                          // M_n complete on s
+        }
+        hipLaunchKernelGGL(als::chol_inverse, dim3(1), dim3(256), 0, as, G, N, n, R,
                            p->rt<double>(L.rt_L), p->rt<double>(L.rt_Linv), p->rt<double>(L.rt_W),
                            p->ridge(), p->fail());
         const int64_t I = L.dims[n];
         const double *W = p->rt<double>(L.rt_W);
         if (bf) {
-            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, as,
                                d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (uint16_t *)d_factors[n]);
-            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, s, colsq,
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, as, colsq,
                                als::APPLY_BLOCKS, R, d_lambda);
-            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+            hipLaunchKernelGGL(als::als_apply<uint16_t>, dim3(als::APPLY_BLOCKS), dim3(256), 0, as,
                                d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (uint16_t *)d_factors[n]);
         } else {
-            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, as,
                                d_mbuf, I, R, RT, W, 0, colsq, d_lambda, (float *)d_factors[n]);
-            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, s, colsq,
+            hipLaunchKernelGGL(als::lambda_kernel, dim3(R), dim3(256), 0, as, colsq,
                                als::APPLY_BLOCKS, R, d_lambda);
-            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, s,
+            hipLaunchKernelGGL(als::als_apply<float>, dim3(als::APPLY_BLOCKS), dim3(256), 0, as,
                                d_mbuf, I, R, RT, W, 1, colsq, d_lambda, (float *)d_factors[n]);
         }
         HIPCHK(p, hipGetLastError());
-        if ((st = gram(n)) != MTTKRP_OK) return st;
+        if ((st = gram(n, as)) != MTTKRP_OK) return st;
+        if (overlap) {
+            p->aux_pending = true;
+            if ((st = remap_step(p, s)) != MTTKRP_OK) return st;   // beside the update
+        }
     }
+    // everything the side stream did is complete on `s` when the call's work
+    // is (the fit below reads M_{N-1} and A_{N-1})
+    if ((st = join_aux(p, s)) != MTTKRP_OK) return st;
     if (d_fit) {
         const int n = N - 1;
         double *inner = colsq;
