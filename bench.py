@@ -366,6 +366,23 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         del uplan
         log(f"unpacked-record fp32 sweep {unpacked_ms:.3f} ms")
 
+    resident = None
+    if not args.no_ablation:
+        # memory for time: keep resident the layout whose incoming remap
+        # measured slowest (one more tensor copy), then every layout (the
+        # paper's "without remapping" case, N + 2 copies), FP32 sweep
+        slow = max(range(N), key=lambda n: per_remap[n][0] / max(per_remap[n][1], 1))
+        resident = {}
+        for name, modes in (("one", [(slow + 1) % N]), ("all", list(range(N)))):
+            mask = sum(_abi.RESIDENT_LAYOUT(n) for n in modes)
+            rplan = Plan(idx, vals, dims, R, g=args.g, flags=flags | mask)
+            rms = timer(lambda: rplan.mttkrp_all_modes(f32, outs), args.steps, args.warmup)
+            resident[name] = {"resident_modes": modes, "sweep_ms": round(rms, 4),
+                              "extra_tensor_copies": len(modes),
+                              "extra_bytes": len(modes) * nnz * rb}
+            log(f"resident layouts {modes}: sweep {rms:.3f} ms")
+            del rplan
+
     locality = None
     if args.locality:
         # plan option: Morton order of the two leading inputs inside each
@@ -543,6 +560,7 @@ def bench_sweep(args, torch, dev, syn, _abi, Plan, oracle):
         "fused_remap_sweep_ms": round(fused_ms, 4) if fused_ms else None,
         "unpacked_records_sweep_ms": round(unpacked_ms, 4) if unpacked_ms else None,
         "locality_order": locality,
+        "resident_layouts": resident,
         "layout_copy_per_mode_sweep_ms": round(ncopy_ms, 4),
         "cp_als": als,
         "sweep_ms_median": round(step_ms[len(step_ms) // 2], 4),

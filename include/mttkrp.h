@@ -103,6 +103,15 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
                                         from the two layouts.  Results are the
                                         same sums in another order.         */
 
+/* Memory for time (plan option): keep a copy of the layout L_n resident in
+ * the workspace for every mode n whose bit is set (bits 16 + n).  Moving to
+ * a resident layout then switches buffers instead of running the remap into
+ * it; results and layouts are unchanged.  Each resident layout costs nnz
+ * stored records of workspace beyond the paper's two buffers (Sec. IV-B);
+ * keeping every mode's layout is the paper's "without dynamic remapping"
+ * case (Sec. V).  EINVAL for a bit at or above nmodes. */
+#define MTTKRP_RESIDENT_LAYOUT(n) (1u << (16 + (n)))
+
 /* Partitioning parameters (Sec. III-A, III-C).  Zero selects a default. */
 typedef struct {
     int32_t g;                       /* nonzeros per shard; default 1024     */

@@ -25,6 +25,11 @@ FUSED_REMAP = 4
 UNPACKED_RECORDS = 8
 GATHER_ONLY = 16
 LOCALITY_ORDER = 32
+
+
+def RESIDENT_LAYOUT(n):
+    """MTTKRP_RESIDENT_LAYOUT(n): keep the layout of mode n resident."""
+    return 1 << (16 + n)
 PROF_MTTKRP, PROF_REMAP, PROF_RESID, PROF_LOSS = 0, 1, 2, 3
 Q_LAYOUT, Q_PERM, Q_ROW_PTR, Q_SHARDS, Q_LPT = range(5)
 INFO_CUR_MODE, INFO_NSHARDS, INFO_NSUPER = 0, 1, 2

@@ -55,6 +55,8 @@ struct Layout {
     uint32_t cmask[MTTKRP_MAX_MODES];  // its mask
     int64_t m[MTTKRP_MAX_MODES], k[MTTKRP_MAX_MODES], maxS[MTTKRP_MAX_MODES];
     size_t off_rec[2], off_perm[MTTKRP_MAX_MODES], off_rp[MTTKRP_MAX_MODES];
+    size_t off_res[MTTKRP_MAX_MODES];   // resident copy of L_n (MTTKRP_RESIDENT_LAYOUT)
+    uint32_t resident;                  // bit n: L_n kept resident
     size_t off_sh[MTTKRP_MAX_MODES], off_ord[MTTKRP_MAX_MODES], off_split[MTTKRP_MAX_MODES];
     size_t off_lpt[MTTKRP_MAX_MODES];
     size_t off_xx, off_misc;           // persistent scalars
@@ -96,6 +98,11 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     L->workers = (opts && opts->workers > 0) ? opts->workers : DEFAULT_WORKERS;
     L->flags = opts ? opts->flags : 0u;
     if (opts && opts->g < 0) { *why = "g must be >= 0"; return MTTKRP_EINVAL; }
+    L->resident = (L->flags >> 16) & 0xffu;
+    if (L->resident >> N) {
+        *why = "MTTKRP_RESIDENT_LAYOUT names a mode >= nmodes";
+        return MTTKRP_EINVAL;
+    }
     for (int n = 0; n < N; ++n) {
         if (dims[n] < 1 || dims[n] >= (int64_t(1) << 31)) {
             *why = "every dimension must be in [1, 2^31)";
@@ -128,6 +135,8 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     L->off_rec[0] = take((size_t)nnz * NW * 4);
     L->off_rec[1] = take((size_t)nnz * NW * 4);
+    for (int n = 0; n < N; ++n)
+        L->off_res[n] = (L->resident >> n & 1u) ? take((size_t)nnz * NW * 4) : 0;
     for (int n = 0; n < N; ++n) L->off_perm[n] = take((size_t)nnz * 4);
     for (int n = 0; n < N; ++n) L->off_rp[n] = take((size_t)(dims[n] + 1) * 4);
     int64_t maxS = 0;
@@ -188,7 +197,7 @@ struct mttkrp_plan_s {
     Layout L;
     char *ws = nullptr;
     int cur = 0;            // layout the tensor is in
-    int buf = 0;            // record buffer holding it
+    int buf = 0;            // record buffer holding it: 0, 1 (work) or 2 + n (resident L_n)
     int64_t nshards[MTTKRP_MAX_MODES] = {};
     int64_t nsplit[MTTKRP_MAX_MODES] = {};   // rows split across shards
     int64_t npart[MTTKRP_MAX_MODES] = {};    // their boundary partials (P0)
@@ -210,7 +219,17 @@ struct mttkrp_plan_s {
     bool aux_pending = false;
     int carry_sel = 0;
 
-    uint32_t *rec(int b) { return reinterpret_cast<uint32_t *>(ws + L.off_rec[b]); }
+    uint32_t *rec(int b)
+    {
+        return reinterpret_cast<uint32_t *>(ws + (b < 2 ? L.off_rec[b] : L.off_res[b - 2]));
+    }
+    // the buffer that holds L_to after the tensor moves there from buffer
+    // `from`: its resident copy, else the work buffer that `from` is not
+    int next_buf(int from, int to) const
+    {
+        if (L.resident >> to & 1u) return 2 + to;
+        return from == 0 ? 1 : 0;
+    }
     int32_t *perm(int n) { return reinterpret_cast<int32_t *>(ws + L.off_perm[n]); }
     int32_t *rp(int n) { return reinterpret_cast<int32_t *>(ws + L.off_rp[n]); }
     int32_t *sh(int n) { return reinterpret_cast<int32_t *>(ws + L.off_sh[n]); }
@@ -634,16 +653,26 @@ static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
     if (p->prof) {
         ev.a = take_event(p);
         ev.b = take_event(p);
-        if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
     }
-    HIPCHK(p, launch_remap_any(L.N, L.cw, p->rec(p->buf), p->rec(p->buf ^ 1), p->perm(p->cur),
-                               L.nnz, s));
+    const int nx = (p->cur + 1) % L.N;
+    const int dst = p->next_buf(p->buf, nx);
+    if (dst >= 2) {
+        // L_nx is resident: nothing to move
+        if (ev.a) p->pool.push_back(ev.a);
+        if (ev.b) p->pool.push_back(ev.b);
+        p->buf = dst;
+        p->cur = nx;
+        return MTTKRP_OK;
+    }
+    if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
+    HIPCHK(p, launch_remap_any(L.N, L.cw, p->rec(p->buf), p->rec(dst), p->perm(p->cur), L.nnz,
+                               s));
     if (p->prof) {
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);
     }
-    p->buf ^= 1;
-    p->cur = (p->cur + 1) % L.N;
+    p->buf = dst;
+    p->cur = nx;
     return MTTKRP_OK;
 }
 
@@ -697,7 +726,10 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
                            rows * L.R);
     if (L.nnz == 0) {
         HIPCHK(p, hipGetLastError());
-        if (fuse) p->cur = (n + 1) % L.N;
+        if (fuse) {
+            p->buf = p->next_buf(p->buf, (n + 1) % L.N);
+            p->cur = (n + 1) % L.N;
+        }
         return MTTKRP_OK;
     }
     mk::Args a;
@@ -706,7 +738,9 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     // default the remap runs as its own kernel right after (faster here)
     const bool infuse = fuse && (L.flags & MTTKRP_FUSED_REMAP);
     a.rin = p->rec(p->buf);
-    a.rout = infuse ? p->rec(p->buf ^ 1) : nullptr;
+    // the in-kernel remap writes L_{n+1} unless that layout is resident
+    const int nbuf = p->next_buf(p->buf, (n + 1) % L.N);
+    a.rout = (infuse && nbuf < 2) ? p->rec(nbuf) : nullptr;
     a.perm = p->perm(n);
     a.row_ptr = p->rp(n);
     a.shards = p->sh(n);
@@ -788,7 +822,7 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
         p->aux_pending = true;
     }
     if (infuse) {
-        p->buf ^= 1;
+        p->buf = nbuf;
         p->cur = (n + 1) % L.N;
     } else if (fuse) {
         return remap_step(p, s);
@@ -1021,6 +1055,25 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
                            L.cw + 1, part);
         hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)nb, p->xx());
     }
+    // resident layouts: one sweep of remaps through the work buffers, each
+    // resident layout copied out as it is reached; L_0 ends in work buffer
+    // N mod 2 (or is read from its resident copy)
+    int buf0 = 0;
+    if (L.resident) {
+        const size_t rbytes = (size_t)nnz * (L.cw + 1) * 4;
+        int b = 0;
+        for (int n = 0; n < N; ++n) {
+            if ((L.resident >> n & 1u) &&
+                hipMemcpyAsync(p->rec(2 + n), p->rec(b), rbytes, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess)
+                return bail(fail(p, MTTKRP_EHIP, "resident layout copy"));
+            if (launch_remap_any(N, L.cw, p->rec(b), p->rec(b ^ 1), p->perm(n), nnz, s) !=
+                hipSuccess)
+                return bail(fail(p, MTTKRP_EHIP, "resident layout remap"));
+            b ^= 1;
+        }
+        buf0 = (L.resident & 1u) ? 2 : b;
+    }
     // 4. host partition tables
     std::vector<int32_t> rp, shards, order, split, bins;
     for (int n = 0; n < N; ++n) {
@@ -1054,7 +1107,7 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
         return MTTKRP_EHIP;
     }
     p->cur = 0;
-    p->buf = 0;
+    p->buf = buf0;
     *out = p;
     return MTTKRP_OK;
 }

@@ -149,3 +149,20 @@ def test_python_constants_match_header():
              "EHIP": _abi.EHIP}
     for name, v in pairs.items():
         assert vals.get(name) == v, (name, vals.get(name), v)
+
+
+def test_resident_layouts_workspace_and_argument_check(lib):
+    """Each resident layout adds one buffer of stored records to the
+    workspace (12-byte records here: 14 coordinate bits in two words); a
+    resident bit at or above nmodes is EINVAL."""
+    dims, nnz = (10, 20, 30), 100000
+    base = _abi.mttkrp_plan_workspace(3, dims, nnz, 16)
+    for mask, k in ((_abi.RESIDENT_LAYOUT(0), 1), (_abi.RESIDENT_LAYOUT(2), 1),
+                    (_abi.RESIDENT_LAYOUT(0) | _abi.RESIDENT_LAYOUT(1) | _abi.RESIDENT_LAYOUT(2),
+                     3)):
+        ws = _abi.mttkrp_plan_workspace(3, dims, nnz, 16, _abi.make_opts(flags=mask))
+        extra = ws - base
+        assert k * nnz * 12 <= extra <= k * (nnz * 12 + 256), (mask, extra)
+    with pytest.raises(_abi.MttkrpError) as ei:
+        _abi.mttkrp_plan_workspace(3, dims, nnz, 16, _abi.make_opts(flags=_abi.RESIDENT_LAYOUT(3)))
+    assert ei.value.status == _abi.EINVAL

@@ -247,3 +247,74 @@ def test_record_bytes_and_layout(dims, words):
             assert np.array_equal(p.query(_abi.Q_LAYOUT),
                                   oracle_layout_records(t, layouts[n])), (flags, n)
             p.remap((n + 1) % N)
+
+
+# N = 3 Zipf, N = 4, N = 5, N = 2, rows over many shards, three reduction levels
+RESIDENT_CASES = [MTT_CASES[1], MTT_CASES[6], MTT_CASES[7], MTT_CASES[8], MTT_CASES[12],
+                  MTT_CASES[13]]
+
+
+def _resident_masks(N):
+    R = _abi.RESIDENT_LAYOUT
+    masks = [R(0), R(N - 1), sum(R(n) for n in range(N))]
+    if N > 2:
+        masks.append(R(1) | R(N - 1))
+    return masks
+
+
+@pytest.mark.parametrize("extra", [0, _abi.FUSED_REMAP])
+@pytest.mark.parametrize("case", RESIDENT_CASES)
+def test_resident_layouts_give_the_same_results(case, extra):
+    """Plans that keep some or all layouts resident: the default plan's
+    outputs bit for bit over repeated sweeps, the oracle's layouts at every
+    step of a standalone remap walk, and implicit remaps to single modes."""
+    dims, nnz, R, seed, distinct, zipf, g = case
+    say("resident case", case, "extra", extra)
+    t = syn.random_tensor(dims, nnz, R, seed, distinct=distinct, zipf_s=zipf)
+    N = len(dims)
+    base, facs = make_plan(t, g=g, flags=extra)
+    ref = [o.clone() for o in base.mttkrp_all_modes(facs)]
+    layouts, _, _ = oracle.remap_replay(dims, t.idx)
+    for mask in _resident_masks(N):
+        p, _ = make_plan(t, g=g, flags=extra | mask)
+        assert np.array_equal(p.query(_abi.Q_LAYOUT), oracle_layout_records(t, layouts[0]))
+        for _ in range(2):
+            outs = p.mttkrp_all_modes(facs)
+            torch.cuda.synchronize()
+            assert p.cur_mode == 0
+            for n in range(N):
+                assert torch.equal(outs[n], ref[n]), (mask, n)
+        for n in range(1, N + 1):
+            p.remap(n % N)
+            assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                                  oracle_layout_records(t, layouts[n])), (mask, n)
+        # implicit remaps: the last mode, then the first again
+        o = p.mttkrp_mode(N - 1, facs, fuse_remap=False)
+        assert torch.equal(o, ref[N - 1])
+        o = p.mttkrp_mode(0, facs)
+        assert torch.equal(o, ref[0]) and p.cur_mode == 1 % N
+
+
+def test_resident_layouts_cp_als_and_loss_unchanged():
+    """CP-ALS sweeps and the loss with its gradients on a plan with resident
+    layouts equal those of the default plan bit for bit."""
+    t = syn.random_tensor((40, 3, 30, 5), 2500, 8, 33, zipf_s=1.2)
+    R = _abi.RESIDENT_LAYOUT
+    base, facs = make_plan(t, g=100)
+    res, _ = make_plan(t, g=100, flags=R(0) | R(2))
+    fa = [f.clone() for f in facs]
+    fb = [f.clone() for f in facs]
+    for _ in range(2):
+        la, ta = base.cp_als_sweep(fa)
+        lb, tb = res.cp_als_sweep(fb)
+    torch.cuda.synchronize()
+    assert torch.equal(la, lb) and torch.equal(ta, tb)
+    for a, b in zip(fa, fb):
+        assert torch.equal(a, b)
+    u = [torch.rand_like(f) for f in facs]
+    l1, g1 = base.cp_loss_grad(u)
+    l2, g2 = res.cp_loss_grad(u)
+    torch.cuda.synchronize()
+    assert l1.item() == l2.item()
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
