@@ -7,12 +7,14 @@ compared on sampled output rows that the oracle computes one by one, and
 on layout invariants that hold at any size.  A mode of 2^26 rows at R = 64
 checks 64-bit addressing (factor and output offsets up to 2^32 elements).
 The CP-ALS driver recovers a fully stored planted tensor of 49.8M nonzeros.
+Workload 3 (the benchmark's) is checked on sampled rows with FP32 and BF16
+factors, and the loss workload on its full loss and sampled gradient rows.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import FP32_TOL, _abi, check_close, dev, oracle, say
+from gpu_common import BF16_TOL, FP32_TOL, _abi, bf16_round, check_close, dev, oracle, say
 from paper_2309_09131_amd import synthetic as syn
 from paper_2309_09131_amd.api import Plan
 
@@ -169,3 +171,66 @@ def test_cp_als_recovers_a_planted_tensor_at_50m_nonzeros():
         b = true[n] / np.linalg.norm(true[n], axis=0)
         cong = np.abs(a.T @ b).max(axis=0)            # best match of each planted column
         assert cong.min() > 0.999, (n, cong)
+
+
+def test_workload3_full_size_sampled_rows_fp32_and_bf16():
+    """The benchmark workload (4 modes, 100M nonzeros, R = 32) in the launch
+    configuration the benchmark times: sampled output rows of every mode
+    (the heaviest and random ones) against the oracle, with FP32 factors and
+    with BF16-stored factors (against the oracle on the FP32 factors and on
+    the BF16-rounded ones); repeated sweeps bit-identical."""
+    T = syn.generate(3)
+    say("workload 3 generated", T.nnz)
+    d = dev()
+    p = Plan(torch.from_numpy(T.idx).to(d), torch.from_numpy(T.vals).to(d), T.dims, T.rank)
+    f32 = [torch.from_numpy(f).to(d) for f in T.factors]
+    bf = [f.to(torch.bfloat16) for f in f32]
+    outs = [o.clone() for o in p.mttkrp_all_modes(f32)]
+    again = p.mttkrp_all_modes(f32)
+    outb = [o.clone() for o in p.mttkrp_all_modes(bf)]
+    frb = [bf16_round(f) for f in T.factors]
+    rng = np.random.default_rng(7)
+    for n in range(4):
+        assert torch.equal(outs[n], again[n])
+        counts = np.bincount(T.idx[n], minlength=T.dims[n])
+        rows = np.unique(np.concatenate([np.argsort(counts)[-4:],
+                                         rng.choice(T.dims[n], 20, replace=False)]))
+        sel = torch.from_numpy(rows).to(d)
+        ref, rabs = oracle.mttkrp_rows(T.dims, T.idx, T.vals, T.factors, n, rows)
+        check_close(outs[n][sel].cpu().numpy(), ref, rabs, FP32_TOL, f"mode {n} fp32")
+        check_close(outb[n][sel].cpu().numpy(), ref, rabs, BF16_TOL, f"mode {n} bf16")
+        refb, rabsb = oracle.mttkrp_rows(T.dims, T.idx, T.vals, frb, n, rows)
+        check_close(outb[n][sel].cpu().numpy(), refb, rabsb, FP32_TOL, f"mode {n} bf16 acc")
+
+
+def test_workload4_full_loss_and_sampled_gradient_rows():
+    """The loss workload (50M nonzeros over 200K^3, planted rank 64, R = 64)
+    at the benchmark's evaluation point: the loss over every nonzero against
+    the oracle, and sampled gradient rows of every mode, which depend only on
+    the nonzeros in those rows, against the oracle run on exactly those
+    nonzeros."""
+    T = syn.generate(4)
+    say("workload 4 generated", T.nnz)
+    d = dev()
+    p = Plan(torch.from_numpy(T.idx).to(d), torch.from_numpy(T.vals).to(d), T.dims, T.rank)
+    facs = [torch.from_numpy(f).to(d) for f in T.factors]
+    loss, grads = p.cp_loss_grad(facs)
+    f64 = [f.astype(np.float64) for f in T.factors]
+    L_ref = oracle.cp_loss_grad(T.dims, T.idx, T.vals, f64, want_grad=False)
+    assert abs(loss.item() - L_ref) <= FP32_TOL * abs(L_ref), (loss.item(), L_ref)
+    rng = np.random.default_rng(8)
+    R = T.rank
+    for k in range(3):
+        counts = np.bincount(T.idx[k], minlength=T.dims[k])
+        rows = np.unique(np.concatenate([np.argsort(counts)[-4:],
+                                         rng.choice(T.dims[k], 12, replace=False)]))
+        keep = np.isin(T.idx[k], rows)
+        sidx, sval = np.ascontiguousarray(T.idx[:, keep]), np.ascontiguousarray(T.vals[keep])
+        _, G = oracle.cp_loss_grad(T.dims, sidx, sval, f64)
+        # |.| scale: 2 * sum over the row's nonzeros of (|x| + sum_r |prod|) |prod_{n!=k}|
+        mabs = np.zeros(sidx.shape[1])
+        for r in range(R):
+            mabs += np.abs(f64[0][sidx[0], r] * f64[1][sidx[1], r] * f64[2][sidx[2], r])
+        _, gabs = oracle.mttkrp(T.dims, sidx, np.abs(sval) + mabs, f64, k, with_abs=True)
+        got = grads[k][torch.from_numpy(rows).to(d)].cpu().numpy()
+        check_close(got, G[k][rows], 2.0 * gabs[rows], FP32_TOL, f"gradient mode {k}")
