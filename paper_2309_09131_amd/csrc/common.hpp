@@ -78,6 +78,82 @@ __device__ __forceinline__ int rec_coord_at(const uint32_t *__restrict__ buf, in
     return (int)((uint32_t)(x >> (off & 31u)) & mask);
 }
 
+// Or a coordinate (which fits its field) into the field at bit offset
+// `off` of a record being built (its coordinate words zeroed first).
+template <int W>
+__device__ __forceinline__ void rec_put(Rec<W> &r, uint32_t off, uint32_t v)
+{
+    const uint32_t q = off >> 5;
+    const uint64_t x = (uint64_t)v << (off & 31u);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        r.w[k] |= (q == (uint32_t)k) ? (uint32_t)x : 0u;
+        r.w[k] |= (q + 1 == (uint32_t)k) ? (uint32_t)(x >> 32) : 0u;
+    }
+}
+
+// An L_n record in L_{n+1}'s format: the coordinates of the modes other than
+// n and nx move from their L_n fields (ioff) to their L_{n+1} fields (ooff),
+// the output row c_n (implied by the position in L_n, passed in `row`) is
+// stored, and c_nx (implied by the position in L_{n+1}) is dropped.
+template <int N, int W>
+__device__ __forceinline__ Rec<W> repack(const Rec<W> &r, int row, int n, int nx,
+                                         const uint32_t *ioff, const uint32_t *ooff,
+                                         const uint32_t *msk)
+{
+    Rec<W> o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) o.w[k] = 0u;
+    o.w[W] = r.w[W];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        if (m == nx) continue;
+        const uint32_t v = (m == n) ? (uint32_t)row : (uint32_t)rec_coord<W>(r, ioff[m], msk[m]);
+        rec_put<W>(o, ooff[m], v);
+    }
+    return o;
+}
+
+// Row-start table lookups (layout described in launch.hpp): the ordinal of
+// the output row holding position e among the mode's nonempty rows, and
+// whether e is the first position of that row, from the table entry
+// {lo, hi, count} of e's block.
+struct RowStart {
+    uint32_t lo, hi, cnt;
+};
+
+__device__ __forceinline__ RowStart row_start_at(const uint32_t *__restrict__ t, int b)
+{
+    const uint32_t *q = t + 3 * (int64_t)b;
+    return RowStart{q[0], q[1], q[2]};
+}
+
+__device__ __forceinline__ int row_ordinal(const RowStart &r, int e, bool &first)
+{
+    const int j = e & 63;
+    const uint64_t bits = ((uint64_t)r.hi << 32) | r.lo;
+    first = ((bits >> j) & 1ull) != 0;
+    return (int)r.cnt + (int)__popcll(bits & ((2ull << j) - 1ull)) - 1;
+}
+
+// Row starts among the 64 positions from offset `off` (0..63) into table
+// block b, from the entries of blocks b and b + 1: bit i of `m` is set when
+// the position i places on starts a row; `before` counts the rows starting
+// before the first of them.
+struct SegStarts {
+    uint64_t m;
+    int before;
+};
+
+__device__ __forceinline__ SegStarts seg_starts(const RowStart &a, const RowStart &b, int off)
+{
+    const uint64_t ba = ((uint64_t)a.hi << 32) | a.lo, bb = ((uint64_t)b.hi << 32) | b.lo;
+    SegStarts s;
+    s.m = off ? ((ba >> off) | (bb << (64 - off))) : ba;
+    s.before = (int)a.cnt + (int)__popcll(ba & ((1ull << off) - 1ull));
+    return s;
+}
+
 // bfloat16 storage <-> float.  Widening is exact (the 16 high bits).
 __device__ __forceinline__ float bf16lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }

@@ -1,15 +1,16 @@
 // Instantiation of the templated kernels for one mode count NM (defined by
 // the including inst_n<NM>.hip), for every record width W of that mode
-// count (rec_wmin(NM) <= W <= NM coordinate words).
+// count (rec_wmin(NM) <= W <= NM - 1 coordinate words).
 #pragma once
 #include "mttkrp_kernels.hpp"
 
 namespace plan {
 
-// L_0 records: rec[j] = (coordinates of input o[j] bit-packed at the
-// offsets pm.off, value of input o[j]).  Every coordinate fits its field
-// (the host sizes the fields from the dimensions and validates the input
-// first), so the fields are simply or-ed in.
+// L_0 records: rec[j] = (coordinates of input o[j] except c_0, which the
+// position implies, bit-packed at the offsets pm.off, value of input o[j]).
+// Every coordinate fits its field (the host sizes the fields from the
+// dimensions and validates the input first), so the fields are simply or-ed
+// in.
 template <int N, int W>
 __global__ void pack_kernel(const int32_t *__restrict__ idx, const float *__restrict__ vals,
                             const int32_t *__restrict__ o, int64_t n, mk::PackMap pm,
@@ -23,6 +24,7 @@ __global__ void pack_kernel(const int32_t *__restrict__ idx, const float *__rest
         for (int k = 0; k < W; ++k) r.w[k] = 0u;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
+            if (m == pm.skip) continue;
             const uint32_t q = pm.off[m] >> 5;
             const uint64_t x = (uint64_t)(uint32_t)idx[(int64_t)m * n + s] << (pm.off[m] & 31u);
 #pragma unroll
@@ -120,17 +122,25 @@ hipError_t launch_width(const Args &a, int bf16, LaneCfg c, int kind, unsigned g
     return launch_contig<W, float, 4>(a, c.lanes, kind, grid, s);
 }
 
-template <int W>
-hipError_t launch_remap_w(const uint32_t *rin, uint32_t *rout, const int32_t *perm, int64_t nnz,
-                          hipStream_t s)
+template <int W, int RT>
+hipError_t launch_remap_rt(const uint32_t *rin, uint32_t *rout, const int32_t *perm,
+                           int64_t nnz, const RemapMap &rm, hipStream_t s)
 {
-    // one block per chunk of 256 * RT records (RT as in remap_kernel), the
-    // grid rounded up to a multiple of the 8 XCDs
-    constexpr int RT = remap_rt<W>();
+    // one block per chunk of 256 * RT records, the grid rounded up to a
+    // multiple of the 8 XCDs
     const int64_t nchunks = (nnz + 256 * RT - 1) / (256 * RT);
     unsigned grid = (unsigned)(((nchunks + 7) / 8) * 8);
-    hipLaunchKernelGGL((remap_kernel<NM, W>), dim3(grid), dim3(256), 0, s, rin, rout, perm, nnz);
+    hipLaunchKernelGGL((remap_kernel<NM, W, RT>), dim3(grid), dim3(256), 0, s, rin, rout, perm,
+                       nnz, rm);
     return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_remap_w(const uint32_t *rin, uint32_t *rout, const int32_t *perm, int64_t nnz,
+                          const RemapMap &rm, hipStream_t s)
+{
+    if (rm.small) return launch_remap_rt<W, remap_rt_of(W, true)>(rin, rout, perm, nnz, rm, s);
+    return launch_remap_rt<W, remap_rt_of(W, false)>(rin, rout, perm, nnz, rm, s);
 }
 
 template <int W>
@@ -143,12 +153,12 @@ hipError_t launch_pack_w(const int32_t *idx, const float *vals, const int32_t *o
     return hipGetLastError();
 }
 
-// The compiled widths of this mode count: NM, NM - 1 and (from five modes
-// on) NM - 2, never below rec_wmin(NM).
-constexpr int W0 = NM;
-constexpr int W1 = NM - 1 >= rec_wmin(NM) ? NM - 1 : NM;
-constexpr int W2 = NM - 2 >= rec_wmin(NM) ? NM - 2 : W1;
-static_assert(rec_wmin(NM) >= NM - 2, "widths W0..W2 cover rec_wmin..NM");
+// The compiled widths of this mode count: NM - 1, NM - 2 and NM - 3, never
+// below rec_wmin(NM).
+constexpr int W0 = NM - 1;
+constexpr int W1 = NM - 2 >= rec_wmin(NM) ? NM - 2 : W0;
+constexpr int W2 = NM - 3 >= rec_wmin(NM) ? NM - 3 : W1;
+static_assert(rec_wmin(NM) >= NM - 3 && rec_wmin(NM) >= 1, "widths W0..W2 cover rec_wmin..NM-1");
 }  // namespace
 
 template <>
@@ -163,12 +173,12 @@ hipError_t launch_mttkrp<NM>(const Args &a, int bf16, LaneCfg c, int kind, unsig
 
 template <>
 hipError_t launch_remap<NM>(const uint32_t *rin, uint32_t *rout, const int32_t *perm,
-                            int64_t nnz, int cw, hipStream_t s)
+                            int64_t nnz, int cw, const RemapMap &rm, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
-    if (cw == W0) return launch_remap_w<W0>(rin, rout, perm, nnz, s);
-    if (cw == W1) return launch_remap_w<W1>(rin, rout, perm, nnz, s);
-    if (cw == W2) return launch_remap_w<W2>(rin, rout, perm, nnz, s);
+    if (cw == W0) return launch_remap_w<W0>(rin, rout, perm, nnz, rm, s);
+    if (cw == W1) return launch_remap_w<W1>(rin, rout, perm, nnz, rm, s);
+    if (cw == W2) return launch_remap_w<W2>(rin, rout, perm, nnz, rm, s);
     return hipErrorInvalidValue;
 }
 

@@ -276,9 +276,9 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     const int n = a.mode, R = a.R;
     const int slot = lane / LANES, sub = lane % LANES;
     const bool ract = lane_active<LANES, V, STRIDED>(sub, R);
-    const uint32_t noff = a.coff[n], nmsk = a.cmask[n];     // output coordinate
-    const int f = rec_coord_at<W>(a.rin, start, noff, nmsk);
-    const int l = rec_coord_at<W>(a.rin, end - 1, noff, nmsk);
+    // the shard's first and last output rows (plan table); records do not
+    // store c_n, which the row-start table of L_n recovers per position
+    const int f = a.fl[2 * shard], l = a.fl[2 * shard + 1];
     const bool split_before = a.row_ptr[f] < start;
     float coef = 1.0f;
     if constexpr (RESID) coef = -2.0f * (a.gscale ? (float)a.gscale[0] : 1.0f);
@@ -293,9 +293,6 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     const int run = (len + SW - 1) / SW;
     const int s0 = start + slot * run;
     const int s1 = min(s0 + run, end);           // s0 >= s1: empty run (row l)
-    int cur_row = (s0 < s1) ? rec_coord_at<W>(a.rin, s0, noff, nmsk) : l;
-    const int head_row = cur_row;
-    bool in_head = true;
     float acc[V], head[V];
 #pragma unroll
     for (int j = 0; j < V; ++j) { acc[j] = 0.0f; head[j] = 0.0f; }
@@ -344,16 +341,57 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
     for (int j = 0; j < RW; ++j) xo[j] = 0u;
     double lacc = 0.0;                            // KIND_LOSS: sum of rho^2
     constexpr int RPL = (U + LANES - 1) / LANES;
+    // Output rows.  A slot's run is walked in segments of 64 positions,
+    // [s0 + 64m, s0 + 64m + 64), which never split a step (64 is a multiple
+    // of U) and span at most two 64-position blocks of the row-start table.
+    // When the positions it loads next open a segment, the slot builds the
+    // segment's 64-bit start mask from two table entries; each step then
+    // takes its U start bits with one shift and keeps a running count of
+    // rows started (the ordinal that indexes the list of nonempty rows).
+    // Every slot of the wave opens its next segment at the same step, so
+    // the mask is built under a wave-uniform branch once per 64 / U steps,
+    // from entries loaded one segment earlier: segment m needs the entries
+    // of blocks sblk + m and sblk + m + 1, held in ev (even offsets) and od
+    // (odd offsets); the one of block sblk + m is then replaced in place by
+    // that of block sblk + m + 2.  (Rotated through a third register, the
+    // new entry went to a temporary whose copy waited for the load.)  The
+    // row id of a position is loaded only where a row starts, and for the
+    // run's first position; elsewhere nid = -1 means "the previous
+    // position's row".
+    constexpr int SEG = 64 / U;                  // steps per segment
+    static_assert(64 % U == 0 && U <= 32, "a step never splits a 64-position segment");
+    const int soff = s0 & 63, sblk = s0 >> 6;
+    RowStart od = row_start_at(a.rbits, min(sblk + 1, a.nblk));
+    RowStart ev = row_start_at(a.rbits, min(sblk + 2, a.nblk));
+    const SegStarts sg0 = seg_starts(row_start_at(a.rbits, min(sblk, a.nblk)), od, soff);
+    uint64_t smask = sg0.m;
+    int orun = sg0.before;                       // rows started before the positions loaded next
     Rec<W> nxt[RPL];
+    int nid[RPL];
+    {
+        const uint32_t bu = (uint32_t)smask & ((1u << U) - 1u);
 #pragma unroll
-    for (int j = 0; j < RPL; ++j) {
-        const int u = sub + j * LANES;
-        const int e = s0 + u;
-        nxt[j] = load_rec<W>(a.rin, (u < U && u < run && e < end) ? e : start);
+        for (int j = 0; j < RPL; ++j) {
+            const int u = sub + j * LANES;
+            const int e = s0 + u;
+            const bool v = u < U && u < run && e < end;
+            nxt[j] = load_rec<W>(a.rin, v ? e : start);
+            const bool st = ((bu >> (u & 31)) & 1u) != 0;
+            const int o = orun + __popc(bu & ((2u << (u & 31)) - 1u)) - 1;
+            nid[j] = -1;
+            if (v && (st || u == 0)) nid[j] = a.nrows[max(o, 0)];   // o >= 0 when v
+        }
+        orun += __popc(bu);
     }
+    const int r0 = __shfl(nid[0], slot * LANES);  // row of the run's first position
+    int cur_row = (s0 < s1) ? r0 : l;
+    const int head_row = cur_row;
+    int prow = cur_row;                          // row of the previous position
+    bool in_head = true;
     for (int k = 0; k < run; k += U) {           // uniform trip count
         Rec<W> rc[U];
         bool ok[U];
+        int rr[U];                               // output row of each nonzero
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = s0 + k + u;
@@ -362,13 +400,41 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 #pragma unroll
             for (int w = 0; w < W + 1; ++w)
                 rc[u].w[w] = (uint32_t)__shfl((int)nxt[u / LANES].w[w], src);
+            const int id = __shfl(nid[u / LANES], src);
+            rr[u] = id >= 0 ? id : (u == 0 ? prow : rr[u - 1]);
         }
+        prow = rr[U - 1];
+        const int q = (k + U) / U;               // step of the positions loaded next
+        if (q % SEG == 0 && q * U < run) {       // they open a segment (uniform)
+            const int m = q / SEG;
+            int ix = min(sblk + m + 2, a.nblk);
+            if (m & 1) {
+                const SegStarts sg = seg_starts(od, ev, soff);
+                smask = sg.m;
+                orun = sg.before;
+                asm volatile("" : "+v"(ix) : "v"(orun));   // load after od is read
+                od = row_start_at(a.rbits, ix);
+            } else {
+                const SegStarts sg = seg_starts(ev, od, soff);
+                smask = sg.m;
+                orun = sg.before;
+                asm volatile("" : "+v"(ix) : "v"(orun));   // load after ev is read
+                ev = row_start_at(a.rbits, ix);
+            }
+        }
+        const uint32_t bu = (uint32_t)(smask >> (U * (q % SEG))) & ((1u << U) - 1u);
 #pragma unroll
         for (int j = 0; j < RPL; ++j) {            // clamped index: no branch
             const int u = sub + j * LANES;
             const int e = s0 + k + U + u;
-            nxt[j] = load_rec<W>(a.rin, (u < U && k + U + u < run && e < end) ? e : start);
+            const bool v = u < U && k + U + u < run && e < end;
+            nxt[j] = load_rec<W>(a.rin, v ? e : start);
+            const bool st = ((bu >> (u & 31)) & 1u) != 0;
+            const int o = orun + __popc(bu & ((2u << (u & 31)) - 1u)) - 1;
+            nid[j] = -1;
+            if (v && st) nid[j] = a.nrows[max(o, 0)];
         }
+        orun += __popc(bu);
         float pr[U][V];
         float mm[U];
         uint32_t xq[OREUSE ? U : 1][RW];
@@ -377,7 +443,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             int co[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                co[u] = rec_coord<W>(rc[u], noff, nmsk);
+                co[u] = rr[u];
                 ndo[u] = ok[u] && co[u] != (u == 0 ? po : co[u - 1]);
             }
 #pragma unroll
@@ -450,9 +516,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                     for (int j = 0; j < RW; ++j) xo[j] = sel ? xq[u][j] : xo[j];
                     RawRow<FT, V>::unpack(xo, xn);
                 } else {
-                    Fetch<FT, V, STRIDED>::get(a.fac[n],
-                                               (int64_t)rec_coord<W>(rc[u], noff, nmsk), R,
-                                               fsub, xn);
+                    Fetch<FT, V, STRIDED>::get(a.fac[n], (int64_t)rr[u], R, fsub, xn);
                 }
 #pragma unroll
                 for (int j = 0; j < V; ++j) mm[u] += pr[u][j] * xn[j];
@@ -475,10 +539,16 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             int dst[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) dst[u] = a.perm[ok[u] ? s0 + k + u : start];
+            const int nx = n + 1 < N ? n + 1 : 0;
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u] && sub == 0) store_rec<W>(a.rout, dst[u], rc[u]);
+                if (ok[u] && sub == 0)
+                    store_rec<W>(a.rout, dst[u],
+                                 repack<N, W>(rc[u], rr[u], n, nx, a.coff, a.ooff, a.cmask));
         }
+        // the weight of each nonzero: its value, or -2 s rho for the
+        // residual kinds (every lane takes part in the slot sums)
+        float cv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             float c = 0.0f;
@@ -495,15 +565,35 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
             } else {
                 if (ok[u]) c = __uint_as_float(rc[u].w[W]);
             }
-            if constexpr (GONLY) {
+            cv[u] = c;
+        }
+        if constexpr (GONLY) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
                 if (ok[u]) {
 #pragma unroll
-                    for (int j = 0; j < V; ++j) acc[j] += c * pr[u][j];
+                    for (int j = 0; j < V; ++j) acc[j] += cv[u] * pr[u][j];
                 }
-                continue;
-            }
+            continue;
+        }
+        // Most steps stay inside the current row: then the products are
+        // simply added.  Only a step that opens a row (or ends the run)
+        // takes the per-nonzero path, which keeps the control flow and the
+        // accumulator moves of row changes off the common path.
+        bool same = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u) same = same && ok[u] && rr[u] == cur_row;
+        if (same) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[j] += cv[u] * pr[u][j];
+            continue;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
             if (ok[u]) {
-                const int row = rec_coord<W>(rc[u], noff, nmsk);
+                const int row = rr[u];
                 if (row != cur_row) {
                     if (in_head) {
 #pragma unroll
@@ -518,7 +608,7 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
                     cur_row = row;
                 }
 #pragma unroll
-                for (int j = 0; j < V; ++j) acc[j] += c * pr[u][j];
+                for (int j = 0; j < V; ++j) acc[j] += cv[u] * pr[u][j];
             }
         }
     }
@@ -596,34 +686,65 @@ __global__ __launch_bounds__(MTT_WAVES * 64) void mttkrp_kernel(Args a)
 // write.  The result does not depend on the store order (every record has
 // its own destination).
 //
-// Records per thread (RT): 24 for 12-byte records, else 16, fewer when the
-// LDS stage of 256 * RT records plus their targets would exceed 96 KB.  The
-// host sizes the grid with the same function.
+
+// An L_n record in L_{n+1}'s format (as repack) for records of at most
+// three coordinate words, as one bit-string operation (parameters in
+// RemapMap) on a 64-bit (W <= 2) or 128-bit (W = 3) integer.
 template <int W>
-__host__ __device__ constexpr int remap_rt()
+struct RecBits {
+    using T = uint64_t;
+};
+template <>
+struct RecBits<3> {
+    using T = unsigned __int128;
+};
+
+template <int W>
+__device__ __forceinline__ Rec<W> repack_bits(const Rec<W> &r, int row, const RemapMap &rm)
 {
-    // 16 measured fastest of 8, 12, 16, 24 and 30 for 16-byte records; 24
-    // for 12-byte ones (1.6% faster than 16, the same as 32)
-    constexpr int RT0 = (W + 1 == 3) ? 24 : 16;
-    constexpr int RTC = (96 * 1024) / (256 * (4 * (W + 1) + 4));
-    return RT0 < RTC ? RT0 : RTC;
+    static_assert(W <= 3, "three coordinate words at most");
+    using T = typename RecBits<W>::T;
+    T x = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x |= (T)r.w[k] << (32 * k);
+    constexpr uint32_t B = 8 * sizeof(T);
+    const T lowm = rm.ba >= B ? ~(T)0 : ((T)1 << rm.ba) - (T)1;
+    const T hm = rm.hi ? ~(T)0 : (T)0;
+    const T y = (x & lowm) | (((x >> rm.bh) << rm.bu) & hm) | ((T)(uint32_t)row << rm.bp);
+    Rec<W> o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) o.w[k] = (uint32_t)(y >> (32 * k));
+    o.w[W] = r.w[W];
+    return o;
 }
 
-// (TU, the mode count of the translation unit, only keeps the symbol of
-// each instantiation unique to one code object.)
-template <int TU, int W>
+// Each record also changes format on the way: c_n (recovered from L_n's
+// row-start table and the plan's row ids) is stored and c_{n+1} (implied by
+// the record's slot in L_{n+1}) dropped.  Wave w of the block reads the
+// RT * 64 consecutive positions from base + w * RT * 64 (a "region"), one
+// 64-position table block per record step, so that one load per lane brings
+// the wave's table entries (read back with readlane), and, when the region
+// covers at most 64 rows (nearly always), one more brings all their row ids
+// (read back with a lane shuffle), with no load depending on another: with
+// one block per CU (its LDS stage), nothing else hides such a chain.  Reads
+// stay coalesced (64 consecutive records per load), and the result does not
+// depend on which thread moves which record.
+// RT records per thread (remap_rt_of in launch.hpp; the host sizes the grid
+// and the per-region row ids with the same function).
+template <int N, int W, int RT>
 __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__ rin,
                                                     uint32_t *__restrict__ rout,
                                                     const int32_t *__restrict__ perm,
-                                                    int64_t nnz)
+                                                    int64_t nnz, RemapMap rm)
 {
-    constexpr int RT = remap_rt<W>();
     constexpr int RB = 256 * RT;
     constexpr int NB = 1024;              // buckets
+    static_assert(RT + 1 <= 64, "a wave's table entries take one load per lane");
     __shared__ Rec<W> srec[RB];
     __shared__ int32_t sdst[RB];
     __shared__ int32_t cnt[NB];
     const int t = threadIdx.x;
+    const int lane = t & 63;
     // XCD-aware chunk order: workgroups are handed to the 8 XCDs round-robin,
     // so block b takes chunk (b % 8) * per + b / 8 and every XCD walks one
     // contiguous range of the tensor.  Records that share a destination line
@@ -634,25 +755,60 @@ __global__ __launch_bounds__(256) void remap_kernel(const uint32_t *__restrict__
     const int64_t chunk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (chunk < nchunks) {
         const int64_t base = chunk * RB;
+        const int64_t wbase = base + (int64_t)(t >> 6) * RT * 64;   // multiple of 64
         for (int k = t; k < NB; k += 256) cnt[k] = 0;
+        // the wave's row ids (plan table) and row-start table entries, one
+        // load per lane each, issued before the records: neither depends on
+        // another load
+        const int rid = rm.rids[(wbase / (RT * 64)) * 64 + lane];
+        RowStart ent{0u, 0u, 0u};
+        if (lane <= RT) {
+            const int64_t b = wbase / 64 + lane;
+            ent = row_start_at(rm.rbits, (int)(b < rm.nblk ? b : rm.nblk));
+        }
         __syncthreads();
         Rec<W> r[RT];
         int32_t d[RT], pos[RT];
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
-            const int64_t i = base + k * 256 + t;
+            const int64_t i = wbase + k * 64 + lane;
             const bool ok = i < nnz;
             // Read-once streams are loaded non-temporal, so they do not
             // evict the partly written destination lines that wait in L2 for
             // their other records, nor the new layout in the Infinity Cache,
             // which the next MTTKRP reads (12-byte records: that kernel
-            // 0.237 -> 0.215 ms).  Records only when they are 12, 16 or 32
-            // bytes: for 20- and 24-byte records non-temporal loads measured
+            // 0.237 -> 0.215 ms).  Records only when they are 8, 12, 16 or
+            // 32 bytes: for 20- and 24-byte records non-temporal loads measured
             // 15-45% slower, also when the chunk was first staged so that
             // every line is read once.
-            if constexpr ((W + 1) % 4 == 0 || W + 1 == 3) r[k] = load_rec_nt<W>(rin, ok ? i : 0);
+            if constexpr ((W + 1) % 4 == 0 || W + 1 <= 3) r[k] = load_rec_nt<W>(rin, ok ? i : 0);
             else r[k] = load_rec<W>(rin, ok ? i : 0);
             d[k] = ok ? __builtin_nontemporal_load(perm + i) : -1;
+        }
+        // The entries cover the wave's RT blocks and the block after them
+        // (past the end: the last entry, which has no bits and the row
+        // count).  The wave's row ordinals start at o_first, the row holding
+        // its first position; rid holds the ids of rows o_first + lane
+        // unless the region covers more than 64 rows (then they are read
+        // from the list of nonempty rows).
+        const int o_first = __builtin_amdgcn_readlane((int)ent.cnt, 0) +
+                            (__builtin_amdgcn_readlane((int)ent.lo, 0) & 1) - 1;
+        const bool staged = __builtin_amdgcn_readlane(rid, 0) >= 0;   // wave-uniform
+        int row[RT];
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            const RowStart e{(uint32_t)__builtin_amdgcn_readlane((int)ent.lo, k),
+                             (uint32_t)__builtin_amdgcn_readlane((int)ent.hi, k),
+                             (uint32_t)__builtin_amdgcn_readlane((int)ent.cnt, k)};
+            bool st;
+            const int o = row_ordinal(e, lane, st);   // position wbase + 64k + lane
+            if (staged) row[k] = __shfl(rid, o - o_first);
+            else row[k] = rm.nrows[(d[k] >= 0) ? o : 0];   // in-range index either way
+        }
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            if constexpr (W <= 3) r[k] = repack_bits<W>(r[k], row[k], rm);
+            else r[k] = repack<N, W>(r[k], row[k], rm.n, rm.nx, rm.ioff, rm.ooff, rm.msk);
         }
 #pragma unroll
         for (int k = 0; k < RT; ++k) {

@@ -51,14 +51,24 @@ struct Layout {
     int workers;
     uint32_t flags;
     int cw;                            // coordinate words per record
-    uint32_t coff[MTTKRP_MAX_MODES];   // bit offset of each coordinate in a record
-    uint32_t cmask[MTTKRP_MAX_MODES];  // its mask
+    // bit offset of coordinate k in a record of layout L_m (L_m's records
+    // omit c_m, implied by the position; loff[m][m] is unused)
+    uint32_t loff[MTTKRP_MAX_MODES][MTTKRP_MAX_MODES];
+    uint32_t cmask[MTTKRP_MAX_MODES];  // mask of coordinate k, 2^b_k - 1
+    uint32_t fw[MTTKRP_MAX_MODES];     // field width of coordinate k (b_k, or 32 unpacked)
+    int64_t nblk;                      // row-start table entries - 1 (ceil(nnz / 64))
+    bool rsmall[MTTKRP_MAX_MODES];     // remap L_n -> L_{n+1} in its small form
+    int64_t nreg[MTTKRP_MAX_MODES];    // its regions (64 * RT positions each)
     int64_t m[MTTKRP_MAX_MODES], k[MTTKRP_MAX_MODES], maxS[MTTKRP_MAX_MODES];
     size_t off_rec[2], off_perm[MTTKRP_MAX_MODES], off_rp[MTTKRP_MAX_MODES];
     size_t off_res[MTTKRP_MAX_MODES];   // resident copy of L_n (MTTKRP_RESIDENT_LAYOUT)
     uint32_t resident;                  // bit n: L_n kept resident
     size_t off_sh[MTTKRP_MAX_MODES], off_ord[MTTKRP_MAX_MODES], off_split[MTTKRP_MAX_MODES];
     size_t off_lpt[MTTKRP_MAX_MODES];
+    size_t off_rb[MTTKRP_MAX_MODES];   // row-start table of L_n
+    size_t off_nr[MTTKRP_MAX_MODES];   // nonempty rows of mode n
+    size_t off_fl[MTTKRP_MAX_MODES];   // first and last row of each shard
+    size_t off_rid[MTTKRP_MAX_MODES];  // row ids of each remap region of L_n
     size_t off_xx, off_misc;           // persistent scalars
     size_t off_scratch, scratch_bytes, total;
     // runtime scratch (inside scratch)
@@ -115,21 +125,41 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
         L->k[n] = (dims[n] + L->m[n] - 1) / L->m[n];
         L->maxS[n] = (nnz + L->g - 1) / L->g + L->k[n];
     }
-    // Record format: the coordinates bit-packed in mode order, b_n = bit
-    // length of I_n - 1 bits each (a coordinate may straddle two words), in
-    // cw words, rounded up to the narrowest compiled width; or one word per
-    // coordinate when the plan asks for it.  A 0-bit coordinate (I_n = 1)
-    // sits at offset 0 with an empty mask.
+    // Record format of layout L_m: the coordinates other than c_m (which the
+    // position in L_m implies, through the row-start table) bit-packed in
+    // mode order, b_k = bit length of I_k - 1 bits each (a coordinate may
+    // straddle two words); or one word per coordinate when the plan asks for
+    // it.  A 0-bit coordinate (I_k = 1) sits at offset 0 with an empty mask.
+    // Every layout uses the same cw: the widest layout's words, rounded up
+    // to the narrowest compiled width.
     const bool unpacked = (L->flags & MTTKRP_UNPACKED_RECORDS) != 0;
-    int tot = 0;
+    int bits[MTTKRP_MAX_MODES];
     for (int n = 0; n < N; ++n) {
         int b = 0;
         while ((int64_t(1) << b) < dims[n]) ++b;
-        L->coff[n] = unpacked ? 32u * n : (b ? (uint32_t)tot : 0u);
+        bits[n] = b;
         L->cmask[n] = b ? (uint32_t)((uint64_t(1) << b) - 1) : 0u;
-        tot += b;
+        L->fw[n] = unpacked ? 32u : (uint32_t)b;
     }
-    L->cw = unpacked ? N : std::max(mk::rec_wmin(N), (tot + 31) / 32);
+    int words = 1;
+    for (int m = 0; m < N; ++m) {
+        int tot = 0, slot = 0;
+        for (int k = 0; k < N; ++k) {
+            if (k == m) { L->loff[m][k] = 0u; continue; }
+            L->loff[m][k] = unpacked ? 32u * slot : (bits[k] ? (uint32_t)tot : 0u);
+            tot += bits[k];
+            ++slot;
+        }
+        words = std::max(words, (tot + 31) / 32);
+    }
+    L->cw = unpacked ? N - 1 : std::max(mk::rec_wmin(N), words);
+    L->nblk = (nnz + 63) / 64;
+    // one region per wave of each remap block (4 waves of RT * 64 records)
+    for (int n = 0; n < N; ++n) {
+        L->rsmall[n] = dims[(n + 1) % N] <= mk::REMAP_SMALL_ROWS;
+        const int64_t rb = 256 * (int64_t)mk::remap_rt_of(L->cw, L->rsmall[n]);
+        L->nreg[n] = 4 * ((nnz + rb - 1) / rb);
+    }
     const int NW = L->cw + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -145,6 +175,10 @@ mttkrp_status compute_layout(int N, const int64_t *dims, int64_t nnz, int R,
         L->off_ord[n] = take((size_t)L->maxS[n] * 4);
         L->off_split[n] = take((size_t)L->maxS[n] * 16);
         L->off_lpt[n] = take((size_t)L->k[n] * 4);
+        L->off_rb[n] = take((size_t)(L->nblk + 1) * mk::RS_WORDS * 4);
+        L->off_nr[n] = take((size_t)(std::min<int64_t>(dims[n], std::max<int64_t>(nnz, 1)) + 1) * 4);
+        L->off_fl[n] = take((size_t)L->maxS[n] * 8);
+        L->off_rid[n] = take((size_t)std::max<int64_t>(L->nreg[n], 1) * 64 * 4);
         maxS = std::max(maxS, L->maxS[n]);
     }
     L->off_xx = take(64);
@@ -236,6 +270,54 @@ struct mttkrp_plan_s {
     int32_t *ord(int n) { return reinterpret_cast<int32_t *>(ws + L.off_ord[n]); }
     int32_t *split(int n) { return reinterpret_cast<int32_t *>(ws + L.off_split[n]); }
     int32_t *lpt(int n) { return reinterpret_cast<int32_t *>(ws + L.off_lpt[n]); }
+    uint32_t *rb(int n) { return reinterpret_cast<uint32_t *>(ws + L.off_rb[n]); }
+    int32_t *nr(int n) { return reinterpret_cast<int32_t *>(ws + L.off_nr[n]); }
+    int32_t *fl(int n) { return reinterpret_cast<int32_t *>(ws + L.off_fl[n]); }
+    int32_t *rid(int n) { return reinterpret_cast<int32_t *>(ws + L.off_rid[n]); }
+    // the standalone remap's map from L_n to L_{n+1}
+    mk::RemapMap remap_map(int n)
+    {
+        mk::RemapMap m;
+        memset(&m, 0, sizeof(m));
+        const int nx = (n + 1) % L.N;
+        for (int k = 0; k < L.N; ++k) {
+            m.ioff[k] = L.loff[n][k];
+            m.ooff[k] = L.loff[nx][k];
+            m.msk[k] = L.cmask[k];
+        }
+        m.rbits = rb(n);
+        m.nrows = nr(n);
+        m.rids = rid(n);
+        m.nblk = (int32_t)L.nblk;
+        m.n = n;
+        m.nx = nx;
+        m.small = L.rsmall[n] ? 1 : 0;
+        // The move as a bit string (records of at most two words).  L_n
+        // stores the modes other than n in mode order, L_{n+1} those other
+        // than n + 1: the fields below bit a stay, c_{n+1}'s (win bits at a)
+        // is dropped, the fields above move to a + gap, c_n goes to bit rpos.
+        uint32_t a = 0, win, gap, rpos;
+        if (nx == 0) {        // c_0 leaves the bottom, c_{N-1} joins the top
+            win = L.fw[0];
+            gap = 0;
+            rpos = 0;
+            for (int k = 1; k < L.N - 1; ++k) rpos += L.fw[k];
+        } else {              // c_{n+1}'s field becomes c_n's
+            for (int k = 0; k < n; ++k) a += L.fw[k];
+            win = L.fw[nx];
+            gap = L.fw[n];
+            rpos = a;
+        }
+        // the kernels use this form for W <= 3, on a B-bit integer
+        const uint32_t B = L.cw <= 2 ? 64u : 128u;
+        const uint32_t top = 32u * (uint32_t)L.cw;      // stored coordinate bits
+        m.ba = a;                                       // a >= B: every bit below
+        m.hi = (a + win < top && a + gap < B) ? 1u : 0u;
+        m.bh = m.hi ? a + win : 0u;
+        m.bu = m.hi ? a + gap : 0u;
+        m.bp = std::min(rpos, B - 1);   // beyond B - 1 only for a 0-bit c_n (c_n = 0)
+        return m;
+    }
     double *xx() { return reinterpret_cast<double *>(ws + L.off_xx); }
     int32_t *ridge() { return reinterpret_cast<int32_t *>(ws + L.off_misc); }
     int32_t *fail() { return reinterpret_cast<int32_t *>(ws + L.off_misc) + 1; }
@@ -291,17 +373,23 @@ static hipError_t launch_mttkrp_any(int N, const mk::Args &a, int bf16, mk::Lane
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_remap_any(int N, int cw, const uint32_t *rin, uint32_t *rout,
-                                   const int32_t *perm, int64_t nnz, hipStream_t s)
+// L_n (in rin) -> L_{n+1} (in rout)
+static hipError_t launch_remap_any(mttkrp_plan_t p, int n, const uint32_t *rin, uint32_t *rout,
+                                   hipStream_t s)
 {
-    switch (N) {
-    case 2: return mk::launch_remap<2>(rin, rout, perm, nnz, cw, s);
-    case 3: return mk::launch_remap<3>(rin, rout, perm, nnz, cw, s);
-    case 4: return mk::launch_remap<4>(rin, rout, perm, nnz, cw, s);
-    case 5: return mk::launch_remap<5>(rin, rout, perm, nnz, cw, s);
-    case 6: return mk::launch_remap<6>(rin, rout, perm, nnz, cw, s);
-    case 7: return mk::launch_remap<7>(rin, rout, perm, nnz, cw, s);
-    case 8: return mk::launch_remap<8>(rin, rout, perm, nnz, cw, s);
+    const Layout &L = p->L;
+    const mk::RemapMap rm = p->remap_map(n);
+    const int32_t *perm = p->perm(n);
+    const int64_t nnz = L.nnz;
+    const int cw = L.cw;
+    switch (L.N) {
+    case 2: return mk::launch_remap<2>(rin, rout, perm, nnz, cw, rm, s);
+    case 3: return mk::launch_remap<3>(rin, rout, perm, nnz, cw, rm, s);
+    case 4: return mk::launch_remap<4>(rin, rout, perm, nnz, cw, rm, s);
+    case 5: return mk::launch_remap<5>(rin, rout, perm, nnz, cw, rm, s);
+    case 6: return mk::launch_remap<6>(rin, rout, perm, nnz, cw, rm, s);
+    case 7: return mk::launch_remap<7>(rin, rout, perm, nnz, cw, rm, s);
+    case 8: return mk::launch_remap<8>(rin, rout, perm, nnz, cw, rm, s);
     }
     return hipErrorInvalidValue;
 }
@@ -310,7 +398,8 @@ static hipError_t launch_pack_any(const Layout &L, const int32_t *idx, const flo
                                   const int32_t *o, uint32_t *rec, hipStream_t s)
 {
     mk::PackMap pm;
-    for (int n = 0; n < 8; ++n) pm.off[n] = n < L.N ? L.coff[n] : 0u;
+    for (int n = 0; n < 8; ++n) pm.off[n] = n < L.N ? L.loff[0][n] : 0u;
+    pm.skip = 0;
     const int64_t nnz = L.nnz;
     switch (L.N) {
     case 2: return mk::launch_pack<2>(idx, vals, o, nnz, rec, L.cw, pm, s);
@@ -549,7 +638,7 @@ static int key_bits(int64_t I)
 static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
                          std::vector<int32_t> &shards, std::vector<int32_t> &order,
                          std::vector<int32_t> &split, std::vector<int32_t> &lpt_bin,
-                         int64_t *nempty, int64_t *nsplit_rows)
+                         std::vector<int32_t> &fl, int64_t *nempty, int64_t *nsplit_rows)
 {
     const int64_t I = L.dims[n], m = L.m[n], k = L.k[n], g = L.g;
     std::vector<int64_t> ss_first(k), ss_cnt(k);
@@ -597,9 +686,12 @@ static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
     };
     std::vector<int32_t> ids, keys;
     int64_t rows_split = 0;
+    fl.resize(2 * S);
     for (int64_t s = 0; s < S; ++s) {
         const int64_t st = shards[3 * s], en = st + shards[3 * s + 1];
         const int64_t f = row_of(st), l = row_of(en - 1);
+        fl[2 * s] = (int32_t)f;
+        fl[2 * s + 1] = (int32_t)l;
         const bool sb = rp[f] < st, sa = rp[l + 1] > en;
         if (sb) {                       // continues a split row: entry 0
             ids.push_back((int32_t)(2 * s));
@@ -617,6 +709,50 @@ static void build_tables(const Layout &L, int n, const std::vector<int32_t> &rp,
     int64_t ne = 0;
     for (int64_t r = 0; r < I; ++r) ne += (rp[r] == rp[r + 1]);
     *nempty = ne;
+}
+
+// Row-start table of L_n and the list of its nonempty rows, from the row
+// pointers (table layout in launch.hpp).  Entry nblk (one past the last
+// block holding a position) carries the total row count and no bits.
+static void build_row_starts(const Layout &L, int n, const std::vector<int32_t> &rp,
+                             std::vector<uint32_t> &tab, std::vector<int32_t> &rows,
+                             std::vector<int32_t> &rids)
+{
+    const int64_t I = L.dims[n], nb = L.nblk;
+    tab.assign((size_t)(nb + 1) * mk::RS_WORDS, 0u);
+    rows.clear();
+    for (int64_t r = 0; r < I; ++r) {
+        if (rp[r] == rp[r + 1]) continue;
+        const int64_t e = rp[r];
+        tab[(size_t)(e >> 6) * mk::RS_WORDS + ((e >> 5) & 1)] |= 1u << (e & 31);
+        rows.push_back((int32_t)r);
+    }
+    uint32_t c = 0;
+    for (int64_t b = 0; b <= nb; ++b) {
+        uint32_t *t = &tab[(size_t)b * mk::RS_WORDS];
+        t[2] = c;
+        c += (uint32_t)(__builtin_popcount(t[0]) + __builtin_popcount(t[1]));
+    }
+    const int64_t total = (int64_t)rows.size();
+    rows.push_back(rows.empty() ? 0 : rows.back());   // one padding entry
+    // row ids of each remap region: rows o_first .. o_first + 63 (the last
+    // repeated), or -1 first when more than 64 rows meet the region
+    const int64_t reg = 64 * (int64_t)mk::remap_rt_of(L.cw, L.rsmall[n]), nnz = L.nnz;
+    rids.assign((size_t)std::max<int64_t>(L.nreg[n], 1) * 64, 0);
+    for (int64_t r = 0; r < L.nreg[n]; ++r) {
+        const int64_t P = r * reg;
+        if (P >= nnz) continue;
+        const uint32_t *t = &tab[(size_t)(P >> 6) * mk::RS_WORDS];
+        const int64_t o_first = (int64_t)t[2] + (t[0] & 1u) - 1;
+        const int64_t pe = std::min(P + reg, nnz);
+        const int64_t o_end = pe == nnz ? total : (int64_t)tab[(size_t)(pe >> 6) * mk::RS_WORDS + 2];
+        int32_t *d = &rids[(size_t)r * 64];
+        if (o_end - o_first > 64) {
+            d[0] = -1;
+            continue;
+        }
+        for (int q = 0; q < 64; ++q) d[q] = rows[(size_t)std::min(o_first + q, o_end - 1)];
+    }
 }
 
 static mttkrp_status check_factors(mttkrp_plan_t p, const void *const *f, int skip_ok, int mode,
@@ -665,8 +801,7 @@ static mttkrp_status remap_step(mttkrp_plan_t p, hipStream_t s)
         return MTTKRP_OK;
     }
     if (ev.a) HIPCHK(p, hipEventRecord(ev.a, s));
-    HIPCHK(p, launch_remap_any(L.N, L.cw, p->rec(p->buf), p->rec(dst), p->perm(p->cur), L.nnz,
-                               s));
+    HIPCHK(p, launch_remap_any(p, p->cur, p->rec(p->buf), p->rec(dst), s));
     if (p->prof) {
         if (ev.b) HIPCHK(p, hipEventRecord(ev.b, s));
         p->events.push_back(ev);
@@ -744,14 +879,19 @@ static mttkrp_status run_pass(mttkrp_plan_t p, const void *const *facs, mttkrp_d
     a.perm = p->perm(n);
     a.row_ptr = p->rp(n);
     a.shards = p->sh(n);
+    a.fl = p->fl(n);
     a.order = (kind == mk::KIND_LOSS) ? nullptr : p->ord(n);
+    a.rbits = p->rb(n);
+    a.nrows = p->nr(n);
+    a.nblk = (int32_t)L.nblk;
     a.nshards = (int32_t)p->nshards[n];
     a.mode = n;
     a.R = L.R;
     a.cw = L.cw;
     for (int w = 0; w < L.N; ++w) {
         a.fac[w] = facs[w];
-        a.coff[w] = L.coff[w];
+        a.coff[w] = L.loff[n][w];
+        a.ooff[w] = L.loff[(n + 1) % L.N][w];
         a.cmask[w] = L.cmask[w];
     }
     a.out = out;
@@ -1055,9 +1195,43 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
                            L.cw + 1, part);
         hipLaunchKernelGGL(als::sum_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)nb, p->xx());
     }
-    // resident layouts: one sweep of remaps through the work buffers, each
-    // resident layout copied out as it is reached; L_0 ends in work buffer
-    // N mod 2 (or is read from its resident copy)
+    // 4. host partition tables, row-start tables
+    std::vector<int32_t> rp, shards, order, split, bins, fl, nrows, rids;
+    std::vector<uint32_t> rtab;
+    for (int n = 0; n < N; ++n) {
+        rp.resize(L.dims[n] + 1);
+        if (hipMemcpyAsync(rp.data(), p->rp(n), rp.size() * 4, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "row pointer copy"));
+        build_tables(L, n, rp, shards, order, split, bins, fl, &p->nempty[n], &p->nsplit[n]);
+        build_row_starts(L, n, rp, rtab, nrows, rids);
+        p->nshards[n] = (int64_t)shards.size() / 3;
+        p->npart[n] = (int64_t)split.size() / 2;
+        if (p->nshards[n] > L.maxS[n]) return bail(fail(p, MTTKRP_EINVAL, "shard bound"));
+        if (hipMemcpyAsync(p->sh(n), shards.data(), shards.size() * 4, hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipMemcpyAsync(p->fl(n), fl.data(), fl.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(p->rb(n), rtab.data(), rtab.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(p->nr(n), nrows.data(), nrows.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(p->rid(n), rids.data(), rids.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(p->ord(n), order.data(), order.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            (!split.empty() && hipMemcpyAsync(p->split(n), split.data(), split.size() * 4,
+                                              hipMemcpyHostToDevice, s) != hipSuccess) ||
+            hipMemcpyAsync(p->lpt(n), bins.data(), bins.size() * 4, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(p, MTTKRP_EHIP, "table upload"));
+    }
+    // resident layouts: one sweep of remaps through the work buffers (which
+    // needs the row-start tables above), each resident layout copied out as
+    // it is reached; L_0 ends in work buffer N mod 2 (or is read from its
+    // resident copy)
     int buf0 = 0;
     if (L.resident) {
         const size_t rbytes = (size_t)nnz * (L.cw + 1) * 4;
@@ -1067,35 +1241,11 @@ mttkrp_status mttkrp_plan(int nmodes, const int64_t *dims, int64_t nnz, const in
                 hipMemcpyAsync(p->rec(2 + n), p->rec(b), rbytes, hipMemcpyDeviceToDevice, s) !=
                     hipSuccess)
                 return bail(fail(p, MTTKRP_EHIP, "resident layout copy"));
-            if (launch_remap_any(N, L.cw, p->rec(b), p->rec(b ^ 1), p->perm(n), nnz, s) !=
-                hipSuccess)
+            if (launch_remap_any(p, n, p->rec(b), p->rec(b ^ 1), s) != hipSuccess)
                 return bail(fail(p, MTTKRP_EHIP, "resident layout remap"));
             b ^= 1;
         }
         buf0 = (L.resident & 1u) ? 2 : b;
-    }
-    // 4. host partition tables
-    std::vector<int32_t> rp, shards, order, split, bins;
-    for (int n = 0; n < N; ++n) {
-        rp.resize(L.dims[n] + 1);
-        if (hipMemcpyAsync(rp.data(), p->rp(n), rp.size() * 4, hipMemcpyDeviceToHost, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return bail(fail(p, MTTKRP_EHIP, "row pointer copy"));
-        build_tables(L, n, rp, shards, order, split, bins, &p->nempty[n], &p->nsplit[n]);
-        p->nshards[n] = (int64_t)shards.size() / 3;
-        p->npart[n] = (int64_t)split.size() / 2;
-        if (p->nshards[n] > L.maxS[n]) return bail(fail(p, MTTKRP_EINVAL, "shard bound"));
-        if (hipMemcpyAsync(p->sh(n), shards.data(), shards.size() * 4, hipMemcpyHostToDevice,
-                           s) != hipSuccess ||
-            hipMemcpyAsync(p->ord(n), order.data(), order.size() * 4, hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            (!split.empty() && hipMemcpyAsync(p->split(n), split.data(), split.size() * 4,
-                                              hipMemcpyHostToDevice, s) != hipSuccess) ||
-            hipMemcpyAsync(p->lpt(n), bins.data(), bins.size() * 4, hipMemcpyHostToDevice, s) !=
-                hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return bail(fail(p, MTTKRP_EHIP, "table upload"));
     }
     if (hipMemsetAsync(p->ridge(), 0, 8, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return bail(fail(p, MTTKRP_EHIP, "plan finish"));
@@ -1486,12 +1636,18 @@ mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst, 
     if (!dst || bytes < (size_t)need) return fail(p, MTTKRP_EINVAL, "destination too small");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (what == MTTKRP_Q_LAYOUT && need > 0) {
-        // stored records are bit-packed: widen to N coordinates + value, in
-        // chunks so that the host buffers stay small for any nnz
-        const int NW = L.cw + 1, N = L.N;
+        // stored records are bit-packed and omit the layout's own coordinate:
+        // widen to N coordinates + value, that coordinate taken from the
+        // row pointers, in chunks so that the host buffers stay small for
+        // any nnz
+        const int NW = L.cw + 1, N = L.N, m = p->cur;
         const int64_t CH = int64_t(1) << 20;
         std::vector<uint32_t> packed((size_t)std::min(CH, L.nnz) * NW);
         std::vector<uint32_t> wide((size_t)std::min(CH, L.nnz) * (N + 1));
+        std::vector<int32_t> rp((size_t)L.dims[m] + 1);
+        HIPCHK(p, hipMemcpyAsync(rp.data(), p->rp(m), rp.size() * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(p, hipStreamSynchronize(s));
+        int64_t row = 0;
         const uint32_t *srec = static_cast<const uint32_t *>(src);
         char *out = static_cast<char *>(dst);
         for (int64_t c0 = 0; c0 < L.nnz; c0 += CH) {
@@ -1502,10 +1658,15 @@ mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst, 
             for (int64_t i = 0; i < cn; ++i) {
                 const uint32_t *r = packed.data() + i * NW;
                 uint32_t *o = wide.data() + i * (N + 1);
+                while (rp[row + 1] <= c0 + i) ++row;     // row holding position c0 + i
                 for (int n = 0; n < N; ++n) {
-                    const uint32_t q = L.coff[n] >> 5;
+                    if (n == m) {
+                        o[n] = (uint32_t)row;
+                        continue;
+                    }
+                    const uint32_t off = L.loff[m][n], q = off >> 5;
                     const uint64_t x = ((uint64_t)r[q + 1] << 32) | r[q];
-                    o[n] = (uint32_t)(x >> (L.coff[n] & 31u)) & L.cmask[n];
+                    o[n] = (uint32_t)(x >> (off & 31u)) & L.cmask[n];
                 }
                 o[N] = r[NW - 1];
             }

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2309_09131_amd import _abi, build
@@ -102,24 +103,75 @@ def _align(x):
     return (x + 255) & ~255
 
 
+# A record of layout L_m holds the coordinates other than c_m; the packed
+# width is the widest layout's, at least 2 words from four modes and N - 3
+# from five.
 @pytest.mark.parametrize("dims, packed_words", [
-    ((50000, 40000, 30000), 2),                 # 16 + 16 + 15 bits
-    ((300000, 200000, 5000), 2),                # 19 + 18 + 13: mode 1 straddles a word
-    ((1 << 30, 1 << 30, 1 << 30), 3),           # 90 bits: no saving
-    ((70000, 90000, 5000, 300), 3),             # 56 bits, but at least N - 1 words
-    ((2000000, 1000000, 100000, 5000, 500), 3),  # 80 bits, N - 2 words from five modes
-    ((1, 5, 1), 2),                             # 0-bit modes
+    ((50000, 40000, 30000), 1),                 # 16 + 16 + 15 bits: at most 32 stored
+    ((300000, 200000, 5000), 2),                # 19 + 18 + 13: 37 bits stored in L_2
+    ((1 << 30, 1 << 30, 1 << 30), 2),           # 60 bits stored: no saving
+    ((70000, 90000, 5000, 300), 2),             # 47 bits stored in L_3
+    ((1000000, 500000, 20000, 2000), 2),        # 20 + 19 + 15 + 11: 54 bits in L_3
+    ((2000000, 1000000, 100000, 5000, 500), 3),  # 71 bits stored in L_4
+    ((1, 5, 1), 1),                             # 0-bit modes
 ])
 def test_record_width_from_dimensions(lib, dims, packed_words):
     """The stored record is (packed coordinate words + 1) * 4 bytes; with
-    MTTKRP_UNPACKED_RECORDS it is (N + 1) * 4.  Only the two record buffers
-    of the workspace depend on it."""
+    MTTKRP_UNPACKED_RECORDS it is N * 4 (one word per stored coordinate and
+    the value).  The two record buffers of the workspace, and the remap's
+    per-region row ids (regions sized from the width), depend on it."""
     nnz, N = 100003, len(dims)
     packed = _abi.mttkrp_plan_workspace(N, dims, nnz, 16)
     wide = _abi.mttkrp_plan_workspace(N, dims, nnz, 16,
                                       _abi.make_opts(flags=_abi.UNPACKED_RECORDS))
-    rec = lambda words: _align(nnz * 4 * (words + 1))
-    assert wide - packed == 2 * (rec(N) - rec(packed_words))
+    assert wide - packed == _width_delta(dims, nnz, N - 1, packed_words)
+
+
+def _remap_rt(W, small):
+    """Records per thread of the standalone remap (the library's rule)."""
+    per = 256 * (4 * (W + 1) + 4)
+    if small:
+        return min(16, 72 * 1024 // per)
+    return min(32 if W + 1 == 2 else 24 if W + 1 == 3 else 16, 96 * 1024 // per)
+
+
+def _width_delta(dims, nnz, w_wide, w_packed):
+    """Workspace bytes that depend on the record width: the two record
+    buffers, and each layout's per-region row ids of its remap (one region
+    of 64 * RT records per remap wave, RT from the width)."""
+    N = len(dims)
+    rec = lambda w: _align(nnz * 4 * (w + 1))
+    d = 2 * (rec(w_wide) - rec(w_packed))
+    for n in range(N):
+        small = dims[(n + 1) % N] <= 1 << 16
+        for w, sgn in ((w_wide, 1), (w_packed, -1)):
+            rb = 256 * _remap_rt(w, small)
+            d += sgn * _align(max(4 * -(-nnz // rb), 1) * 64 * 4)
+    return d
+
+
+def _stored_words(dims):
+    """Packed words from the width rule, written out independently."""
+    N = len(dims)
+    bits = [max(int(d - 1).bit_length(), 0) for d in dims]
+    w = max((sum(bits) - bits[m] + 31) // 32 for m in range(N))
+    wmin = N - 3 if N >= 5 else (2 if N == 4 else 1)
+    return max(w, wmin, 1)
+
+
+def test_record_width_rule_over_many_shapes(lib):
+    """The packed width for random shapes of 2 to 8 modes follows the rule:
+    the widest layout's stored coordinates, rounded up to the narrowest
+    compiled width."""
+    rng = np.random.default_rng(3)
+    nnz = 4099
+    for _ in range(60):
+        N = int(rng.integers(2, 9))
+        dims = tuple(int(x) for x in rng.integers(1, 1 << int(rng.integers(1, 31)), N))
+        packed = _abi.mttkrp_plan_workspace(N, dims, nnz, 8)
+        wide = _abi.mttkrp_plan_workspace(N, dims, nnz, 8,
+                                          _abi.make_opts(flags=_abi.UNPACKED_RECORDS))
+        assert wide - packed == _width_delta(dims, nnz, N - 1, _stored_words(dims)), dims
 
 
 def test_python_constants_match_header():
@@ -153,8 +205,8 @@ def test_python_constants_match_header():
 
 def test_resident_layouts_workspace_and_argument_check(lib):
     """Each resident layout adds one buffer of stored records to the
-    workspace (12-byte records here: 14 coordinate bits in two words); a
-    resident bit at or above nmodes is EINVAL."""
+    workspace (8-byte records here: at most 10 stored coordinate bits in one
+    word); a resident bit at or above nmodes is EINVAL."""
     dims, nnz = (10, 20, 30), 100000
     base = _abi.mttkrp_plan_workspace(3, dims, nnz, 16)
     for mask, k in ((_abi.RESIDENT_LAYOUT(0), 1), (_abi.RESIDENT_LAYOUT(2), 1),
@@ -162,7 +214,7 @@ def test_resident_layouts_workspace_and_argument_check(lib):
                      3)):
         ws = _abi.mttkrp_plan_workspace(3, dims, nnz, 16, _abi.make_opts(flags=mask))
         extra = ws - base
-        assert k * nnz * 12 <= extra <= k * (nnz * 12 + 256), (mask, extra)
+        assert k * nnz * 8 <= extra <= k * (nnz * 8 + 256), (mask, extra)
     with pytest.raises(_abi.MttkrpError) as ei:
         _abi.mttkrp_plan_workspace(3, dims, nnz, 16, _abi.make_opts(flags=_abi.RESIDENT_LAYOUT(3)))
     assert ei.value.status == _abi.EINVAL

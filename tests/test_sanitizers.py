@@ -121,7 +121,7 @@ namespace mk {
     template <> hipError_t launch_mttkrp<N>(const Args &, int, LaneCfg, int, unsigned,   \\
                                             hipStream_t) { return hipErrorNotSupported; } \\
     template <> hipError_t launch_remap<N>(const uint32_t *, uint32_t *, const int32_t *, \\
-                                           int64_t, int, hipStream_t)                     \\
+                                           int64_t, int, const RemapMap &, hipStream_t)   \\
     { return hipErrorNotSupported; }                                                      \\
     template <> hipError_t launch_pack<N>(const int32_t *, const float *, const int32_t *, \\
                                           int64_t, uint32_t *, int, PackMap, hipStream_t)  \\
