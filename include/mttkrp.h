@@ -76,10 +76,10 @@ typedef enum { MTTKRP_F32 = 0, MTTKRP_BF16 = 1 } mttkrp_dtype;
                                         kernel (the paper's same-agent remap)
                                         instead of a remap kernel right after
                                         it (default: measured faster here)  */
-#define MTTKRP_UNPACKED_RECORDS 8u   /* one 32-bit word per coordinate in the
-                                        stored records instead of the default
-                                        bit-packed form (see the workspace
-                                        description); for comparison       */
+#define MTTKRP_UNPACKED_RECORDS 8u   /* one 32-bit word per stored
+                                        coordinate instead of the default
+                                        bit-packed form (see mttkrp_plan);
+                                        for comparison                     */
 #define MTTKRP_GATHER_ONLY 16u       /* measurement only: MTTKRP passes run a
                                         kernel that issues the MTTKRP kernel's
                                         record loads and factor-row gathers
@@ -138,12 +138,16 @@ mttkrp_status mttkrp_plan_workspace(int nmodes, const int64_t *dims, int64_t nnz
  * (c_0, c_{N-1}, ..., c_1, input position)), for every mode n the remap
  * target P_n (slot of each L_n element in L_{n+1}), row pointers, the
  * super-shard / shard tables and the longest-first schedule (Alg.
- * "ss_scheduling").  The inputs are copied; they may be freed afterwards.
- * A stored nonzero record holds its N coordinates bit-packed (b_n = bit
- * length of I_n - 1 bits each, in mode order, in as few 32-bit words as
- * the compiled widths allow: at least N-1 words, N-2 from five modes on)
- * followed by the FP32 value; MTTKRP_UNPACKED_RECORDS stores one word per
- * coordinate.  Every layout and remap moves these records unchanged.
+ * "ss_scheduling"), and per layout the tables that give the output row of
+ * any position.  The inputs are copied; they may be freed afterwards.
+ * A stored nonzero record of layout L_m holds the N-1 coordinates other
+ * than c_m, which its position implies (L_m is ordered by c_m first),
+ * bit-packed (b_n = bit length of I_n - 1 bits each, in mode order, in as
+ * few 32-bit words as the compiled widths allow for the widest layout: at
+ * least 2 words at four modes, N-3 from five modes on) followed by the FP32
+ * value; MTTKRP_UNPACKED_RECORDS stores one word per stored coordinate.
+ * The remap L_n -> L_{n+1} stores c_n in each record it moves and drops
+ * c_{n+1}.
  * The workspace must stay allocated and untouched while the plan lives.
  * Synchronous: returns after the device work finished.  ERANGE if a
  * coordinate is out of range (nothing else is then valid).
@@ -274,8 +278,9 @@ enum {
 };
 /* Copies the array `what` of `mode` into dst (device or host memory,
  * hipMemcpyDefault; synchronises `stream`).  Sizes in bytes: LAYOUT
- * nnz*(N+1)*4 (the layout the tensor is currently in, its bit-packed
- * records widened to one int32 per coordinate on the host), PERM nnz*4, ROW_PTR
+ * nnz*(N+1)*4 (the layout the tensor is currently in, its stored records
+ * widened on the host to one int32 per coordinate, the layout's own
+ * coordinate taken from its row pointers), PERM nnz*4, ROW_PTR
  * (I_mode+1)*4, SHARDS nshards*12, LPT k_mode*4.  EINVAL if bytes is
  * smaller. */
 mttkrp_status mttkrp_plan_query(mttkrp_plan_t p, int what, int mode, void *dst,
