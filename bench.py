@@ -107,11 +107,12 @@ def host_cpu():
 
 
 def source_sha():
-    """Hash of the MTTKRP kernel sources with comments and blank lines
-    removed: a comment edit does not make the counter summary stale."""
+    """Hash of the MTTKRP kernel sources and of the host library (which
+    picks the kernel forms) with comments and blank lines removed: a
+    comment edit does not make the counter summary stale."""
     h = hashlib.sha256()
     here = os.path.join(ROOT, "paper_2309_09131_amd", "csrc")
-    for f in ("common.hpp", "mttkrp_kernels.hpp", "inst.hpp", "launch.hpp"):
+    for f in ("common.hpp", "mttkrp_kernels.hpp", "inst.hpp", "launch.hpp", "mttkrp_lib.hip"):
         with open(os.path.join(here, f), encoding="utf-8") as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in text.splitlines():

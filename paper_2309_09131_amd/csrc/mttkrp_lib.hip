@@ -578,18 +578,21 @@ static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 static mk::LaneCfg lane_cfg(int R, mttkrp_dtype fdt, const void *const *facs, int N,
                             const float *out)
 {
-    // Lanes per nonzero = R / 8 when possible: FP32 rows are then read 32
-    // bytes per lane (two 16-byte loads), BF16 rows 16 bytes per lane.  The
-    // vector-memory address unit limits this kernel, and this choice issues
-    // the fewest load instructions per nonzero.  Otherwise 16-byte lanes,
-    // else the strided form for ranks that are not a multiple of the vector
-    // width.
+    // FP32 rows with two or three modes: lanes per nonzero = R / 8, each
+    // reading 32 bytes (two 16-byte loads).  From four modes on, and for
+    // BF16 rows: 16 bytes per lane (R / 4 or R / 8 lanes), which needs fewer
+    // registers per nonzero (4-mode FP32 kernel: 127 against 187 VGPRs, 4
+    // waves per SIMD instead of 2).  Measured, FP32 sweeps with 16-byte
+    // against 32-byte lanes: 4 modes R 32 10.18 against 10.42 ms, 5 modes R
+    // 16 23.96 against 25.33 ms, 3 modes R 32 1.05 against 0.99 ms (the
+    // 3-mode R 64 loss step 12.92 against 13.04 ms).  Otherwise the strided
+    // form, for ranks that are not a multiple of the vector width.
     const bool bf = fdt == MTTKRP_BF16;
     const int V16 = bf ? 8 : 4;                  // elements per 16 bytes
     bool ok = (R % V16 == 0) && (out == nullptr || aligned16(out));
     for (int w = 0; w < N && ok; ++w)
         if (facs[w] && !aligned16(facs[w])) ok = false;
-    if (ok && !bf && R % 8 == 0 && next_pow2(R / 8) <= 32)
+    if (ok && !bf && N <= 3 && R % 8 == 0 && next_pow2(R / 8) <= 32)
         return mk::LaneCfg{next_pow2(R / 8), 2, false};
     if (ok && next_pow2(R / V16) <= 64) return mk::LaneCfg{next_pow2(R / V16), 1, false};
     return mk::LaneCfg{64, (R + 63) / 64, true};
