@@ -68,16 +68,6 @@ __device__ __forceinline__ int rec_coord(const Rec<W> &r, uint32_t off, uint32_t
     return (int)((uint32_t)(x >> (off & 31u)) & mask);
 }
 
-// The same coordinate read straight from record i of a buffer.
-template <int W>
-__device__ __forceinline__ int rec_coord_at(const uint32_t *__restrict__ buf, int64_t i,
-                                            uint32_t off, uint32_t mask)
-{
-    const uint32_t *p = buf + i * (W + 1) + (off >> 5);
-    const uint64_t x = ((uint64_t)p[1] << 32) | p[0];
-    return (int)((uint32_t)(x >> (off & 31u)) & mask);
-}
-
 // Or a coordinate (which fits its field) into the field at bit offset
 // `off` of a record being built (its coordinate words zeroed first).
 template <int W>
