@@ -233,6 +233,52 @@ def test_one_output_buffer_for_every_mode(flags):
         check_close(outs[2].cpu().numpy(), ref, rabs, FP32_TOL, "last mode")
 
 
+def _random_case(seed):
+    """A small tensor of random shape: 2 to 8 modes, some tiny and some with
+    more rows than nonzeros (empty rows), any shard size (1 up to 1024, not
+    only multiples of 64), ranks for every lane form, and a record form."""
+    rng = np.random.default_rng(1000 + seed)
+    N = int(rng.choice([2, 3, 3, 4, 4, 5, 6, 8]))
+    dims = tuple(int(rng.choice([1, 2, 5, 37, 300, 2000, 70000])) for _ in range(N))
+    if max(dims) == 1:
+        dims = dims[:-1] + (40,)
+    nnz = int(rng.integers(1, 4000))
+    distinct = bool(rng.random() < 0.5)
+    if distinct:
+        nnz = min(nnz, int(np.prod(dims, dtype=np.float64) // 2) + 1)
+    R = int(rng.choice([1, 3, 4, 8, 12, 16, 20, 32, 48, 64]))
+    g = int(rng.choice([1, 3, 7, 63, 64, 65, 100, 257, 1024]))
+    zipf = float(rng.choice([0.0, 1.3]))
+    flags = int(rng.choice([0, _abi.FUSED_REMAP, _abi.UNPACKED_RECORDS]))
+    return dims, nnz, R, distinct, zipf, g, flags
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_shapes_rows_and_layouts(seed):
+    """Randomly shaped small tensors: every mode's MTTKRP against the oracle
+    and every layout of a full remap cycle byte-exact, so that the output
+    rows the kernels recover from the row-start tables (shards that start
+    and end anywhere in a 64-position block, one-nonzero shards, empty rows)
+    and the records the remap rewrites are both checked."""
+    dims, nnz, R, distinct, zipf, g, flags = _random_case(seed)
+    say("random case", seed, dims, nnz, R, distinct, zipf, g, flags)
+    t = syn.random_tensor(dims, nnz, R, 500 + seed, distinct=distinct, zipf_s=zipf)
+    p, facs = make_plan(t, g=g, flags=flags)
+    outs = p.mttkrp_all_modes(facs)
+    torch.cuda.synchronize()
+    N = len(dims)
+    for n in range(N):
+        ref, rabs = oracle.mttkrp(dims, t.idx, t.vals, t.factors, n, with_abs=True)
+        check_close(outs[n].cpu().numpy(), ref, rabs, FP32_TOL, f"mode {n}")
+    layouts, _, _ = oracle.remap_replay(dims, t.idx)
+    assert p.cur_mode == 0
+    assert np.array_equal(p.query(_abi.Q_LAYOUT), oracle_layout_records(t, layouts[0]))
+    for n in range(1, N + 1):
+        p.remap(n % N)
+        assert np.array_equal(p.query(_abi.Q_LAYOUT),
+                              oracle_layout_records(t, layouts[n])), n
+
+
 @pytest.mark.parametrize("dims, words", [((50000, 40000, 30000), 1),
                                          ((300000, 200000, 5000), 2),
                                          ((70000, 90000, 5000, 300), 2),
