@@ -463,3 +463,47 @@ def test_loss_and_gradient_bf16_factors(case):
         gk = grads[k].cpu().numpy()
         check_close(gk, refs[k][0], refs[k][1], FP32_TOL, f"bf16 grad {k}")
         assert np.linalg.norm(gk - G32[k]) <= BF16_TOL * np.linalg.norm(G32[k])
+
+
+def _random_loss_case(seed):
+    """Randomly shaped small tensors for the residual kinds, which resolve
+    the output row of every nonzero (2 to 6 modes, empty rows, shard sizes
+    that are not multiples of 64, ranks for every lane form)."""
+    rng = np.random.default_rng(2000 + seed)
+    N = int(rng.choice([2, 3, 3, 4, 5, 6]))
+    dims = tuple(int(rng.choice([1, 3, 37, 300, 2000, 50000])) for _ in range(N))
+    if max(dims) == 1:
+        dims = dims[:-1] + (60,)
+    nnz = int(rng.integers(1, 3000))
+    R = int(rng.choice([1, 4, 8, 16, 24, 32, 64]))
+    g = int(rng.choice([1, 5, 63, 65, 200, 1024]))
+    flags = int(rng.choice([0, _abi.FUSED_REMAP, _abi.UNPACKED_RECORDS]))
+    return dims, nnz, R, g, flags
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_shapes_loss_gradient_and_bf16(seed):
+    """On randomly shaped tensors: the loss and every gradient against the
+    oracle (two routes), and BF16-stored factors' MTTKRP against the oracle
+    on the BF16-rounded factors."""
+    dims, nnz, R, g, flags = _random_loss_case(seed)
+    say("random loss case", seed, dims, nnz, R, g, flags)
+    t = syn.random_tensor(dims, nnz, R, 700 + seed, distinct=False, factors="uniform")
+    idx, vals, facs = to_dev(t)
+    p = Plan(idx, vals, dims, R, g=g, flags=flags)
+    f64 = [f.astype(np.float64) for f in t.factors]
+    L_ref, G_ref = oracle.cp_loss_grad(dims, t.idx, t.vals, f64)
+    loss, grads = p.cp_loss_grad(facs)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - L_ref) <= FP32_TOL * abs(L_ref), (loss.item(), L_ref)
+    refs = _grad_ref(t, f64)
+    for k in range(len(dims)):
+        g_ = grads[k].cpu().numpy()
+        assert np.linalg.norm(g_ - G_ref[k]) <= FP32_TOL * max(np.linalg.norm(G_ref[k]), 1e-30)
+        check_close(g_, refs[k][0], refs[k][1], FP32_TOL, f"grad {k}")
+    bf = [f.to(torch.bfloat16) for f in facs]
+    outs = p.mttkrp_all_modes(bf)
+    fb = [bf16_round(f) for f in t.factors]
+    for n in range(len(dims)):
+        ref, rabs = oracle.mttkrp(dims, t.idx, t.vals, fb, n, with_abs=True)
+        check_close(outs[n].float().cpu().numpy(), ref, rabs, FP32_TOL, f"bf16 mode {n}")
