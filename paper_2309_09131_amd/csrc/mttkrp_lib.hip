@@ -584,9 +584,10 @@ static mk::LaneCfg lane_cfg(int R, mttkrp_dtype fdt, const void *const *facs, in
     // registers per nonzero (4-mode FP32 kernel: 127 against 187 VGPRs, 4
     // waves per SIMD instead of 2).  Measured, FP32 sweeps with 16-byte
     // against 32-byte lanes: 4 modes R 32 10.18 against 10.42 ms, 5 modes R
-    // 16 23.96 against 25.33 ms, 3 modes R 32 1.05 against 0.99 ms (the
-    // 3-mode R 64 loss step 12.92 against 13.04 ms).  Otherwise the strided
-    // form, for ranks that are not a multiple of the vector width.
+    // 16 23.96 against 25.33 ms, 3 modes R 32 1.05 against 0.99 ms and R 64
+    // 1.61 against 1.46 ms (the 3-mode R 64 loss step within 1%).  Otherwise
+    // the strided form, for ranks that are not a multiple of the vector
+    // width.
     const bool bf = fdt == MTTKRP_BF16;
     const int V16 = bf ? 8 : 4;                  // elements per 16 bytes
     bool ok = (R % V16 == 0) && (out == nullptr || aligned16(out));
