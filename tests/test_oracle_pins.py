@@ -110,6 +110,7 @@ def test_mttkrp_rank_one_dense_closed_form():
 def test_mttkrp_abs_scale_and_row_subset():
     dims = (40, 30, 20)
     t = syn.random_tensor(dims, 2000, 5, seed=8)
+    t.vals = t.vals - 0.5                         # values of both signs
     full, fabs = oracle.mttkrp(dims, t.idx, t.vals, t.factors, 1, with_abs=True)
     X = dense_from_coo(dims, t.idx, t.vals)
     ref_abs = mttkrp_einsum(np.abs(X), [np.abs(f) for f in t.factors], 1)
@@ -350,6 +351,29 @@ def test_cp_als_planted_exact_recovery_and_monotone_residual():
     for n in range(3):
         assert _congruence(fac[n], true[n]) > 0.9999
         assert np.allclose(np.linalg.norm(fac[n], axis=0), 1.0)
+
+
+def test_cp_als_zero_column_takes_the_ridge_and_matches_rank_minus_one():
+    """A zero column r in the last factor makes every mode's V singular
+    (row and column r of the Hadamard product vanish), so each mode update
+    needs the ridge.  Column r stays zero with lambda_r = 0, and since the
+    ridge is 1e-12 of the mean diagonal, the other columns, lambda and the
+    fit equal the sweep of the same tensor at rank R - 1 without column r."""
+    dims, R, r0 = (9, 8, 7), 4, 2
+    t = syn.random_tensor(dims, 300, R, seed=12)
+    fac = [np.array(f, np.float64) for f in t.factors]
+    fac[2][:, r0] = 0.0
+    got, lam, fit, ridge, _ = oracle.cp_als_sweep(dims, t.idx, t.vals, fac)
+    keep = [r for r in range(R) if r != r0]
+    ref, rlam, rfit, rridge, _ = oracle.cp_als_sweep(dims, t.idx, t.vals,
+                                                     [f[:, keep] for f in fac])
+    assert ridge == 3 and rridge == 0
+    assert lam[r0] == 0.0
+    for n in range(3):
+        assert np.all(got[n][:, r0] == 0.0)
+        assert np.allclose(got[n][:, keep], ref[n], rtol=1e-8, atol=1e-10)
+    assert np.allclose(lam[keep], rlam, rtol=1e-8)
+    assert abs(fit - rfit) < 1e-9
 
 
 def test_cp_als_fit_matches_dense_residual_on_sparse_tensor():
