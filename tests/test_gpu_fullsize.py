@@ -9,7 +9,13 @@ checks 64-bit addressing (factor and output offsets up to 2^32 elements).
 The CP-ALS driver recovers a fully stored planted tensor of 49.8M nonzeros.
 Workload 3 (the benchmark's) is checked on sampled rows with FP32 and BF16
 factors, and the loss workload on its full loss and sampled gradient rows.
+Workload 5 (five modes, 200M nonzeros; opt-in, since its generation alone
+takes about two minutes) is checked on sampled rows of every mode's MTTKRP,
+and its CP-ALS sweep on the normal equations of the last mode's update at
+sampled rows.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -234,3 +240,60 @@ def test_workload4_full_loss_and_sampled_gradient_rows():
         _, gabs = oracle.mttkrp(T.dims, sidx, np.abs(sval) + mabs, f64, k, with_abs=True)
         got = grads[k][torch.from_numpy(rows).to(d)].cpu().numpy()
         check_close(got, G[k][rows], 2.0 * gabs[rows], FP32_TOL, f"gradient mode {k}")
+
+
+@pytest.mark.skipif(os.environ.get("MTTKRP_SLOW_TESTS") != "1",
+                    reason="opt-in with MTTKRP_SLOW_TESTS=1: generating the 200M-nonzero "
+                           "tensor takes about two minutes of host time")
+def test_workload5_full_size_sampled_rows_and_cp_als_update():
+    """The five-mode workload (200M nonzeros, R = 16) in the benchmark's
+    launch configuration: sampled output rows of every mode against the
+    oracle with FP32 and BF16-stored factors, then one CP-ALS sweep (Alg.
+    cp-als, normal-equation reading).  After the sweep the last mode's
+    update must satisfy its normal equations at sampled rows,
+    (A_4 diag(lambda)) V = M_4 with V the Hadamard product of the final
+    Gram matrices of modes 0-3 and M_4 the oracle's MTTKRP on the final
+    factors; its columns have unit norm."""
+    T = syn.generate(5)
+    say("workload 5 generated", T.nnz)
+    d = dev()
+    N, R = T.nmodes, T.rank
+    p = Plan(torch.from_numpy(T.idx).to(d), torch.from_numpy(T.vals).to(d), T.dims, R)
+    f32 = [torch.from_numpy(f).to(d) for f in T.factors]
+    bf = [f.to(torch.bfloat16) for f in f32]
+    outs = [o.clone() for o in p.mttkrp_all_modes(f32)]
+    outb = [o.clone() for o in p.mttkrp_all_modes(bf)]
+    frb = [bf16_round(f) for f in T.factors]
+    rng = np.random.default_rng(9)
+    for n in range(N):
+        counts = np.bincount(T.idx[n], minlength=T.dims[n])
+        rows = np.unique(np.concatenate([np.argsort(counts)[-4:],
+                                         rng.choice(T.dims[n], 12, replace=False)]))
+        sel = torch.from_numpy(rows).to(d)
+        ref, rabs = oracle.mttkrp_rows(T.dims, T.idx, T.vals, T.factors, n, rows)
+        check_close(outs[n][sel].cpu().numpy(), ref, rabs, FP32_TOL, f"mode {n} fp32")
+        check_close(outb[n][sel].cpu().numpy(), ref, rabs, BF16_TOL, f"mode {n} bf16")
+        refb, rabsb = oracle.mttkrp_rows(T.dims, T.idx, T.vals, frb, n, rows)
+        check_close(outb[n][sel].cpu().numpy(), refb, rabsb, FP32_TOL, f"mode {n} bf16 acc")
+    del outs, outb, bf
+    say("workload 5 MTTKRP rows checked")
+    fac = [f.clone() for f in f32]
+    lam, _ = p.cp_als_sweep(fac)
+    F = [f.cpu().numpy().astype(np.float64) for f in fac]
+    lam = lam.cpu().numpy()
+    assert np.all(lam > 0)
+    assert np.allclose(np.linalg.norm(F[N - 1], axis=0), 1.0, rtol=1e-5)
+    V = np.ones((R, R))
+    for w in range(N - 1):
+        V *= F[w].T @ F[w]
+    counts = np.bincount(T.idx[N - 1], minlength=T.dims[N - 1])
+    rows = np.unique(np.concatenate([np.argsort(counts)[-4:],
+                                     rng.choice(T.dims[N - 1], 12, replace=False)]))
+    M, Mabs = oracle.mttkrp_rows(T.dims, T.idx, T.vals, F, N - 1, rows)
+    u = F[N - 1][rows] * lam
+    lhs = u @ V
+    # |.| scale: the FP32 rounding of the stored row, carried through V, and
+    # the FP32 MTTKRP's accumulation
+    scale = np.abs(u) @ np.abs(V) + Mabs
+    err = np.abs(lhs - M)
+    assert np.all(err <= FP32_TOL * scale), float((err / scale).max())
