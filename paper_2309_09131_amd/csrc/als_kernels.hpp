@@ -178,8 +178,18 @@ __device__ __forceinline__ void st<uint16_t>(uint16_t *A, int64_t i, double x)
 // X = M W row by row (FP64).  pass 0: colsq[block][r] = sum of X(i,r)^2 over
 // the block's rows.  pass 1: A(i,r) = X(i,r) / lambda_r (lambda_r = 0: X).
 // Threads: RT per row (RT >= R, a power of two), RP = 256 / RT rows at a
-// time; the RP rows of M are staged in LDS with one coalesced load each,
-// and W sits in LDS when it fits (R <= 64).
+// time; thread (g, r) takes the rows i0 + g, i0 + g + RP, ... of its block
+// in that order and sums X(i,r) over q = 0..R-1 in order, so the results do
+// not depend on the form below.
+//   R <= 32 (W in 8 KB of LDS): the RT lanes of a row, inside one wave, each
+//   load one element of it, and X(i,r) takes M(i,q) from lane q by a
+//   cross-lane read; each thread keeps four rows' loads in flight and the
+//   loop has no barrier.  (Staging every RP rows in LDS between two barriers
+//   left the kernel latency-bound at about 0.4 TB/s on a 2M-row factor.)
+//   The small LDS footprint lets several blocks share a CU with the remap
+//   kernel (96 KB of LDS) that runs beside this update.
+//   R > 32: the RP rows are staged in LDS with one coalesced load each and W
+//   is read from memory.
 template <typename FT>
 __global__ __launch_bounds__(256) void als_apply(const float *__restrict__ M, int64_t I, int R,
                                                  int RT, const double *__restrict__ W,
@@ -188,27 +198,54 @@ __global__ __launch_bounds__(256) void als_apply(const float *__restrict__ M, in
                                                  FT *__restrict__ A)
 {
     __shared__ double red[256];
-    __shared__ double sW[64 * 64];
+    __shared__ double sW[32 * 32];
     __shared__ float sM[256];                  // RP * R <= 256 because RT >= R
     const int r = threadIdx.x % RT, g = threadIdx.x / RT, RP = 256 / RT;
-    const bool wl = R <= 64;
+    const bool wl = R <= 32;
     if (wl)
         for (int e = threadIdx.x; e < R * R; e += 256) sW[e] = W[e];
     __syncthreads();
-    const double *Wp = wl ? sW : W;
     const double lam = (pass == 1 && r < R) ? lambda[r] : 1.0;
     double acc = 0.0;
     const int64_t per = (I + gridDim.x - 1) / gridDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * per;
     const int64_t i1 = (i0 + per < I) ? i0 + per : I;
-    for (int64_t ib = i0; ib < i1; ib += RP) {
+    if (wl) {                                    // uniform branch
+        const bool on = r < R;
+        const int base = (threadIdx.x & 63) - r; // lane of the row's element 0
+        constexpr int U = 4;
+        for (int64_t i = i0 + g; i < i1; i += (int64_t)U * RP) {
+            float m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = i + (int64_t)u * RP;
+                m[u] = (on && row < i1) ? M[row * R + r] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t row = i + (int64_t)u * RP;
+                if (row >= i1) break;            // the row's lanes leave together
+                double x = 0.0;
+                for (int q = 0; q < R; ++q) {
+                    const float mq = __shfl(m[u], base + q, 64);
+                    const double w = on ? sW[q * R + r] : 0.0;
+                    x += (double)mq * w;
+                }
+                if (on) {
+                    if (pass == 0) acc += x * x;
+                    else st<FT>(A, row * R + r, lam > 0.0 ? x / lam : x);
+                }
+            }
+        }
+    }
+    for (int64_t ib = i0; !wl && ib < i1; ib += RP) {
         const int nrow = (int)((ib + RP < i1) ? RP : i1 - ib);
         for (int e = threadIdx.x; e < nrow * R; e += 256) sM[e] = M[ib * R + e];
         __syncthreads();
         if (r < R && g < nrow) {
             const float *m = sM + g * R;
             double x = 0.0;
-            for (int q = 0; q < R; ++q) x += (double)m[q] * Wp[q * R + r];
+            for (int q = 0; q < R; ++q) x += (double)m[q] * W[q * R + r];
             if (pass == 0) acc += x * x;
             else st<FT>(A, (ib + g) * R + r, lam > 0.0 ? x / lam : x);
         }

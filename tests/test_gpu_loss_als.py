@@ -154,7 +154,9 @@ def test_loss_at_planted_truth_matches_noise_level():
 
 
 ALS_CASES = [((60, 50, 40), 5000, 8, 91, 64), ((30, 4, 25, 20), 4000, 16, 92, 100),
-             ((80, 70, 60, 10, 5), 8000, 16, 93, 128), ((120, 100), 3000, 5, 94, 64)]
+             ((80, 70, 60, 10, 5), 8000, 16, 93, 128), ((120, 100), 3000, 5, 94, 64),
+             # R > 64: the update's staged form (W read from memory)
+             ((120, 100, 90), 20000, 72, 96, 128)]
 
 
 @pytest.mark.parametrize("case", ALS_CASES)
