@@ -22,47 +22,61 @@ __device__ __forceinline__ double ld<uint16_t>(const uint16_t *A, int64_t i)
     return (double)bf16_to_f32(A[i]);
 }
 
-// Partial Gram over a row range: grid = (gb, tiles, tiles), 256 threads as
-// a 16 x 16 tile of G.  Rows are staged 64 at a time in LDS (coalesced,
-// clamped loads), then every thread accumulates its entry from LDS.
+// Partial Gram over a row range: grid = (gb, tiles, tiles), 256 threads;
+// block (b, y, z) computes the 16 x 16 tile p0 = 16 y, q0 = 16 z of
 // part[b][p][q] = sum_{i in chunk b} A[i][p] A[i][q].
+// The tile is a dense contraction over rows, so it runs on the FP64 matrix
+// cores: one v_mfma_f64_16x16x4f64 adds X Y with X[p][k] = A[i_k][p0 + p]
+// and Y[k][q] = A[i_k][q0 + q] for four rows i_k, and lane l supplies row
+// i_{l/16} at column l % 16 of both operands (one coalesced 64-byte piece of
+// each of the four rows).  Wave w of the block takes the rows
+// i0 + 16 j + 4 w + k, eight steps of four rows in flight; the four waves'
+// tiles are added in LDS in wave order.  Lane l then holds the tile entries
+// (l / 16 + 4 v, l % 16), v = 0..3 (checked on the device against a CPU
+// product).  Columns beyond R and rows beyond the chunk enter as zeros.
+static_assert(GRAM_TILE == 16, "the Gram tile is one 16 x 16 FP64 MFMA tile");
 template <typename FT>
 __global__ __launch_bounds__(256) void gram_partial(const FT *__restrict__ A, int64_t I, int R,
                                                     int64_t chunk, double *__restrict__ part)
 {
-    __shared__ double sp[64][GRAM_TILE + 1], sq[64][GRAM_TILE + 1];
-    const int tx = threadIdx.x % GRAM_TILE, ty = threadIdx.x / GRAM_TILE;
-    const int p0 = blockIdx.y * GRAM_TILE, q0 = blockIdx.z * GRAM_TILE;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double red[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p0 = blockIdx.y * 16, q0 = blockIdx.z * 16;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = (i0 + chunk < I) ? i0 + chunk : I;
-    double acc = 0.0;
-    for (int64_t ib = i0; ib < i1; ib += 64) {
-        double vp[4], vq[4];
+    const int c = lane % 16, kr = lane / 16;
+    const bool okp = p0 + c < R, okq = q0 + c < R;
+    const int pc = okp ? p0 + c : R - 1, qc = okq ? q0 + c : R - 1;
+    const bool diag = p0 == q0;                  // uniform: Y's values are X's
+    constexpr int UN = 8;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t ib = i0 + 4 * w; ib < i1; ib += 16 * UN) {   // uniform trip count
+        double a[UN], b[UN];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = threadIdx.x + k * 256;
-            const int row = e / GRAM_TILE, col = e % GRAM_TILE;
-            const int64_t i = ib + row;
-            const bool okr = i < i1;
-            const int64_t ic = okr ? i : i0;
-            const int pc = (p0 + col < R) ? p0 + col : R - 1;
-            const int qc = (q0 + col < R) ? q0 + col : R - 1;
-            const double a = ld<FT>(A, ic * R + pc), b = ld<FT>(A, ic * R + qc);
-            vp[k] = (okr && p0 + col < R) ? a : 0.0;
-            vq[k] = (okr && q0 + col < R) ? b : 0.0;
+        for (int u = 0; u < UN; ++u) {
+            const int64_t i = ib + 16 * u + kr;
+            const bool ok = i < i1;
+            const int64_t ic = ok ? i : i0;      // clamped: in bounds
+            const double x = ld<FT>(A, ic * R + pc);
+            a[u] = (ok && okp) ? x : 0.0;
+            if (!diag) {
+                const double y = ld<FT>(A, ic * R + qc);
+                b[u] = (ok && okq) ? y : 0.0;
+            } else {
+                b[u] = a[u];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = threadIdx.x + k * 256;
-            sp[e / GRAM_TILE][e % GRAM_TILE] = vp[k];
-            sq[e / GRAM_TILE][e % GRAM_TILE] = vq[k];
-        }
-        __syncthreads();
-#pragma unroll 16
-        for (int rr = 0; rr < 64; ++rr) acc += sp[rr][ty] * sq[rr][tx];
-        __syncthreads();
+        for (int u = 0; u < UN; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
     }
-    if (p0 + ty < R && q0 + tx < R) part[((int64_t)blockIdx.x * R + p0 + ty) * R + q0 + tx] = acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][(lane / 16 + 4 * v) * 16 + lane % 16] = acc[v];
+    __syncthreads();
+    const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+    if (p0 + ty < R && q0 + tx < R)
+        part[((int64_t)blockIdx.x * R + p0 + ty) * R + q0 + tx] =
+            ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
 // G[t] = sum_b part[b][t]: one block per entry, strided partial sums then a
