@@ -36,6 +36,8 @@ MUTANTS = [
      "out[k * R + r] = p;"),
     ("mttkrp rows: factors added instead of multiplied", "p *= a; pa *= fabs(a);",
      "p += a; pa *= fabs(a);"),
+    ("mttkrp rows: a repeated row listed only at its last listing",
+     "if (k0 == k) continue;", "continue;"),
     # layouts (Sec. III-B, Alg. Dynasor remap)
     ("layout L_0: keys in the wrong cyclic direction",
      "int m = (k == 0) ? 0 : g_N - k;", "int m = (k == 0) ? 0 : k;"),
@@ -44,6 +46,8 @@ MUTANTS = [
     ("row pointers: prefix sum stops one row short",
      "for (int64_t i = 0; i < dims[n]; ++i) rp[i + 1] += rp[i];",
      "for (int64_t i = 0; i + 1 < dims[n]; ++i) rp[i + 1] += rp[i];"),
+    ("remap target: the source slot recorded instead of the destination",
+     "perm[(int64_t)n * nnz + i] = dst;", "perm[(int64_t)n * nnz + i] = i;"),
     # locality order (Sec. V-J, Z-Morton)
     ("locality: both coordinates on the even Morton bits",
      "z |= (uint64_t)((a >> k) & 1u) << (2 * k + 1);",
@@ -68,6 +72,8 @@ MUTANTS = [
      "if (w != n || 1)"),
     ("cp-als: lambda is the squared column norm", "lambda[r] = sqrt(s);",
      "lambda[r] = s;"),
+    ("cp-als: Gram matrix keeps only its diagonal", "G[p * R + q] = s;",
+     "G[p * R + q] = (p == q) ? s : 0.0;"),
     ("cp-als: Cholesky column not divided by the pivot", "V[i * R + j] = s / d;",
      "V[i * R + j] = s;"),
     ("cp-als: back substitution with L instead of its transpose",
@@ -87,6 +93,7 @@ MUTANTS = [
     ("loss: gradient multiplies in the differentiated factor", "if (n != k)",
      "if (n != k || 1)"),
     ("loss: model sums only the first rank", "m += p;", "m += (r == 0) ? p : 0.0;"),
+    ("loss: |rho| summed instead of rho^2", "L += rho * rho;", "L += fabs(rho);"),
 ]
 
 RUNNER = r"""
